@@ -1,0 +1,99 @@
+"""Batched scans: many predicates over many resident columns in one persistent
+launch (optionally replayed from a HIP graph), and the autotuner that picks its
+launch shape.
+
+The work list (item, tile) and the rewritten literals are prepared once on the
+host (``bst_batch_prepare``); ``launch`` enqueues a counter reset and one
+persistent kernel whose waves take ``tiles_per_grab`` tiles at a time from a
+shared counter, so columns of very different lengths balance across the chip.
+"""
+from __future__ import annotations
+
+import itertools
+import time
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .column import make_pred, stream_handle
+
+
+class Batch:
+    """specs: sequence of (DeviceColumn, op, lo, hi, in_mask tensor or None); outs: bitvector tensors."""
+
+    def __init__(self, specs, outs, device="cuda"):
+        if len(specs) != len(outs) or not specs:
+            raise ValueError("need one output per scan")
+        self.specs = list(specs)
+        self.outs = list(outs)
+        n = len(specs)
+        self.ws = torch.empty(int(L.bst_batch_workspace_bytes(n)), dtype=torch.uint8, device=device)
+        cols = [s[0].h for s in specs]
+        preds = [make_pred(s[1], s[2], s[3]) for s in specs]
+        masks = [s[4] for s in specs]
+        self.h = L.bst_batch_prepare(cols, preds, masks, outs, self.ws)
+        self.rows = sum(int(s[0].n_rows) for s in specs)
+
+    def launch(self, grid: int = 0, tiles_per_grab: int = 0, use_graph: bool = False, stream=None):
+        L.bst_batch_launch(self.h, int(grid), int(tiles_per_grab), use_graph, stream_handle(stream))
+
+    def close(self):
+        if self.h:
+            L.bst_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def time_call(fn, repeats: int = 5, warmup: int = 1, stream=None) -> float:
+    """Median wall time of fn() on the GPU in milliseconds (HIP events)."""
+    s = stream if stream is not None else torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    samples = []
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        fn()
+        e1.record(s)
+        e1.synchronize()
+        samples.append(e0.elapsed_time(e1))
+    return float(np.median(samples))
+
+
+def autotune(batch: Batch, grids=None, grabs=(1, 2, 4, 8, 16), repeats: int = 5, use_graph: bool = True):
+    """Time every (grid, tiles_per_grab) pair and return the fastest with all timings.
+
+    The chosen pair is also stored as the library's default batch shape.
+    """
+    if grids is None:
+        cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+        grids = [cus * k for k in (2, 4, 8, 16)]
+    results = {}
+    for g, t in itertools.product(grids, grabs):
+        results[(g, t)] = time_call(lambda: batch.launch(g, t, use_graph), repeats=repeats)
+    best = min(results, key=results.get)
+    L.bst_tune_set(L.TUNE_BATCH_GRID, best[0])
+    L.bst_tune_set(L.TUNE_BATCH_GRAB, best[1])
+    return best, results
+
+
+def autotune_scan_grid(col, op="lt", lo=0, hi=None, grids=None, repeats: int = 5):
+    """Pick the single-column scan grid (workgroups per launch) by timing."""
+    if grids is None:
+        cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+        grids = [cus * k for k in (2, 4, 8, 16, 32)]
+    out = col.new_bv()
+    results = {}
+    for g in grids:
+        L.bst_tune_set(L.TUNE_SCAN_GRID, g)
+        results[g] = time_call(lambda: col.scan(op, lo, hi, out=out), repeats=repeats)
+    best = min(results, key=results.get)
+    L.bst_tune_set(L.TUNE_SCAN_GRID, best)
+    return best, results

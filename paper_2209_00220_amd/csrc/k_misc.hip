@@ -1,0 +1,445 @@
+// Fills, bitvector helpers, compaction, lookup, the advisor's timing loop and
+// the device half of the C ABI.
+#include <mutex>
+#include <vector>
+
+#include "device_common.h"
+
+using namespace bst;
+using namespace bst::dev;
+
+namespace bst {
+namespace dev {
+
+// ------------------------------------------------------------ fills
+// ALL / NONE predicates: out = (in_mask or every row) / 0.
+__global__ __launch_bounds__(kBlock) void k_fill(uint64_t* __restrict__ out, const uint64_t* __restrict__ in_mask,
+                                                 uint64_t n, int all) {
+    const uint64_t nwords = (n + 63) >> 6;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t v = all ? valid_mask(w, n) : 0ull;
+        if (all && in_mask) v &= in_mask[w];
+        out[w] = v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bv_binop(const uint64_t* __restrict__ a, const uint64_t* __restrict__ b,
+                                                     uint64_t* __restrict__ out, uint64_t n, int op) {
+    const uint64_t nwords = (n + 63) >> 6;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t v = op == 0 ? (a[w] & b[w]) : (a[w] | b[w]);
+        out[w] = v & valid_mask(w, n);
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int count) {
+    if ((int)threadIdx.x < count) p[threadIdx.x] = 0;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bv_popcount(const uint64_t* __restrict__ bv, uint64_t n,
+                                                        unsigned long long* __restrict__ count) {
+    const uint64_t nwords = (n + 63) >> 6;
+    uint32_t s = 0;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += (uint64_t)gridDim.x * blockDim.x)
+        s += __builtin_popcountll(bv[w] & valid_mask(w, n));
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(count, (unsigned long long)s);
+}
+
+// ------------------------------------------------------------ compaction
+// Ascending row IDs of the set bits: per-tile popcounts, one exclusive scan,
+// then every wave writes its tile's IDs at the tile's offset.
+__global__ __launch_bounds__(kBlock) void k_tile_popc(const uint64_t* __restrict__ bv, uint64_t n,
+                                                      uint64_t* __restrict__ counts, uint64_t ntiles) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t nwords = (n + 63) >> 6;
+    for (uint64_t t = uniform(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)); t < ntiles;
+         t += (uint64_t)gridDim.x * kWavesPerBlock) {
+        const uint64_t d = t * 64 + lane;
+        uint32_t v = d < nwords * 2 ? reinterpret_cast<const uint32_t*>(bv)[d] : 0u;
+        if (d / 2 < nwords) v &= (uint32_t)(valid_mask(d / 2, n) >> (32 * (d & 1)));
+        const uint32_t s = wave_sum(__builtin_popcount(v));
+        if (lane == 0) counts[t] = s;
+    }
+}
+
+// Exclusive scan of counts[0..ntiles) into offsets[0..ntiles], by one workgroup.
+__global__ __launch_bounds__(1024) void k_scan_offsets(const uint64_t* __restrict__ counts, uint64_t ntiles,
+                                                       uint64_t* __restrict__ offsets,
+                                                       unsigned long long* __restrict__ total_out) {
+    __shared__ uint64_t part[1024];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t per = (ntiles + 1023) / 1024;
+    const uint64_t lo = std::min<uint64_t>(ntiles, tid * per), hi = std::min<uint64_t>(ntiles, lo + per);
+    uint64_t s = 0;
+    for (uint64_t i = lo; i < hi; ++i) s += counts[i];
+    part[tid] = s;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024; off <<= 1) {
+        uint64_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    uint64_t run = part[tid] - s;
+    for (uint64_t i = lo; i < hi; ++i) {
+        offsets[i] = run;
+        run += counts[i];
+    }
+    if (tid == 1023) {
+        offsets[ntiles] = part[1023];
+        if (total_out) *total_out = part[1023];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_write_ids(const uint64_t* __restrict__ bv, uint64_t n,
+                                                      const uint64_t* __restrict__ offsets, uint64_t ntiles,
+                                                      uint32_t* __restrict__ ids, uint64_t cap,
+                                                      uint32_t* __restrict__ status) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t nwords = (n + 63) >> 6;
+    for (uint64_t t = uniform(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)); t < ntiles;
+         t += (uint64_t)gridDim.x * kWavesPerBlock) {
+        const uint64_t d = t * 64 + lane;
+        uint32_t v = d < nwords * 2 ? reinterpret_cast<const uint32_t*>(bv)[d] : 0u;
+        if (d / 2 < nwords) v &= (uint32_t)(valid_mask(d / 2, n) >> (32 * (d & 1)));
+        // exclusive prefix of popcounts across lanes
+        uint32_t c = __builtin_popcount(v), incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(incl, o, 64);
+            if ((int)lane >= o) incl += y;
+        }
+        uint64_t pos = offsets[t] + (incl - c);
+        const uint32_t row0 = (uint32_t)(d * 32);
+        bool over = false;
+        while (v) {
+            const uint32_t b = __builtin_ctz(v);
+            v &= v - 1;
+            if (pos < cap) ids[pos] = row0 + b; else over = true;
+            ++pos;
+        }
+        if (over && status) atomicOr(status, BST_DEV_OVERFLOW);
+    }
+}
+
+
+__global__ __launch_bounds__(kBlock) void k_lookup(const DevCol c, const uint32_t* __restrict__ ids, uint64_t m,
+                                                   const unsigned long long* __restrict__ dev_m, uint64_t cap,
+                                                   uint32_t* __restrict__ out, uint32_t* __restrict__ status) {
+    uint64_t cnt = m;
+    if (dev_m) cnt = std::min<uint64_t>((uint64_t)*dev_m, cap);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t r = ids[i];
+        if (r >= c.n) {
+            out[i] = 0;
+            if (status) atomicOr(status, BST_DEV_BAD_ROW);
+            continue;
+        }
+        out[i] = lookup_row(c, r);
+    }
+}
+
+DeviceProps& props() {
+    static DeviceProps p;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            p.cus = cus;
+    });
+    return p;
+}
+
+int64_t g_tune[BST_TUNE_NKEYS] = {0, 0, 0, 4};
+
+PackedLit packed_literal(const HostColumn& h, const ScanLit& s) {
+    PackedLit p{0, 0, (uint32_t)s.negate, 0};
+    const uint64_t maxc = (h.width >= 32) ? 0xffffffffull : ((1ull << h.width) - 1);
+    switch (s.mode) {
+        case kModeNone:
+            p.none = 1;
+            break;
+        case kModeAll:
+            p.a = 0;
+            p.span = 0xffffffffu;
+            p.negate = 0;
+            break;
+        case kModeLT:   // code < lo  <=>  code in [0, lo-1]
+            if (s.lo == 0) { p.a = 1; p.span = 0; p.none = !s.negate; if (s.negate) { p.a = 0; p.span = 0xffffffffu; p.negate = 0; } }
+            else { p.a = 0; p.span = (uint32_t)(s.lo - 1); }
+            break;
+        case kModeGT:   // code > lo  <=>  code in [lo+1, max]
+            if (s.lo >= maxc) { p.none = !s.negate; if (s.negate) { p.a = 0; p.span = 0xffffffffu; p.negate = 0; } }
+            else { p.a = (uint32_t)(s.lo + 1); p.span = (uint32_t)(maxc - s.lo - 1); }
+            break;
+        case kModeEQ:
+            p.a = (uint32_t)s.lo;
+            p.span = 0;
+            break;
+        case kModeBetween:
+            if (s.lo > s.hi) { p.none = 1; break; }
+            p.a = (uint32_t)s.lo;
+            p.span = (uint32_t)(s.hi - s.lo);
+            break;
+    }
+    return p;
+}
+
+int enqueue_fill(uint64_t* out, const uint64_t* in, uint64_t n, int all, hipStream_t st) {
+    const uint64_t nwords = (n + 63) >> 6;
+    hipLaunchKernelGGL(k_fill, dim3(elem_grid(nwords)), dim3(kBlock), 0, st, out, in, n, all);
+    return hip_check(hipGetLastError(), "fill launch");
+}
+
+int run_scan(const bst_column* col, const ScanLit& lit, const uint64_t* in, uint64_t* out,
+             unsigned long long* counters, hipStream_t st) {
+    const DevCol& c = col->dev;
+    if (c.n == 0) return BST_OK;
+    if (lit.mode == kModeNone || lit.mode == kModeAll) return enqueue_fill(out, in, c.n, lit.mode == kModeAll ? 1 : 0, st);
+    if (c.layout == BST_BITPACKED) return launch_packed(c, packed_literal(*col->host, lit), in, out, counters, st);
+    return launch_slices(c, lit, in, out, counters, st);
+}
+
+uint32_t batch_kind(const bst_column* col, const ScanLit& lit) {
+    if (col->dev.layout == BST_BITPACKED) return 16 + col->dev.width;
+    int mi = lit.mode == kModeLT ? 0 : lit.mode == kModeGT ? 1 : lit.mode == kModeEQ ? 2 : 3;
+    return (uint32_t)((col->dev.layout == BST_BYTESLICE ? 1 : 0) | (mi << 1));
+}
+
+}  // namespace dev
+}  // namespace bst
+
+extern "C" {
+
+int bst_device_count(void) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+    return n;
+}
+
+int bst_upload(const bst_host_column* hc, void* const dev_bufs[BST_NBUF], void* stream, bst_column** out) {
+    if (!hc || !dev_bufs || !out) return set_error(BST_EINVAL, "NULL argument");
+    const HostColumn& h = hc->c;
+    hipStream_t st = (hipStream_t)stream;
+    for (int s = 0; s < BST_NBUF; ++s) {
+        if (h.buf[s].empty()) continue;
+        if (!dev_bufs[s]) return set_error(BST_EINVAL, "missing device buffer for slot " + std::to_string(s));
+        int rc = hip_check(hipMemcpyAsync(dev_bufs[s], h.buf[s].data(), h.buf[s].size(), hipMemcpyHostToDevice, st),
+                           "upload");
+        if (rc) return rc;
+    }
+    bst_column* col = new (std::nothrow) bst_column;
+    if (!col) return set_error(BST_ENOMEM, "out of host memory");
+    memset(&col->dev, 0, sizeof(col->dev));
+    col->hc = hc;
+    col->host = &h;
+    DevCol& c = col->dev;
+    c.layout = h.layout;
+    c.width = h.width;
+    c.K = h.K;
+    c.dir_shift = 0;
+    while ((1u << c.dir_shift) < h.dir_stride) ++c.dir_shift;
+    c.domain_mode = h.domain_mode;
+    c.trie_root = h.trie_root;
+    c.n = h.n;
+    c.ntiles = h.ntiles;
+    c.bs[1] = (const uint8_t*)dev_bufs[BST_BUF_BS1];
+    for (uint32_t j = 2; j <= BST_KMAX; ++j) {
+        c.bs[j] = (const uint8_t*)dev_bufs[BST_BUF_BS2 + j - 2];
+        c.m[j] = (const uint64_t*)dev_bufs[BST_BUF_M2 + j - 2];
+        c.dir[j] = (const uint32_t*)dev_bufs[BST_BUF_DIR2 + j - 2];
+    }
+    c.packed = (const uint32_t*)dev_bufs[BST_BUF_PACKED];
+    c.dict = (const uint32_t*)dev_bufs[BST_BUF_DICT];
+    c.trie = (const uint32_t*)dev_bufs[BST_BUF_TRIE];
+    hipGetDevice(&col->device);
+    *out = col;
+    return BST_OK;
+}
+
+void bst_column_free(bst_column* col) { delete col; }
+
+int bst_column_info_get(const bst_column* col, bst_column_info* info) {
+    if (!col) return set_error(BST_EINVAL, "NULL column");
+    return bst_host_info(col->hc, info);
+}
+
+int bst_scan(const bst_column* col, bst_pred pred, const uint64_t* in_mask, uint64_t* out_bv,
+             uint32_t* dev_status, void* stream) {
+    (void)dev_status;
+    if (!col) return set_error(BST_EINVAL, "NULL column");
+    if (col->dev.n && !out_bv) return set_error(BST_EINVAL, "NULL output bitvector");
+    ScanLit lit;
+    int rc = rewrite_predicate(*col->host, pred, &lit);
+    if (rc) return rc;
+    return run_scan(col, lit, in_mask, out_bv, nullptr, (hipStream_t)stream);
+}
+
+int bst_scan_codes(const bst_column* col, int op, uint64_t code_lo, uint32_t len_lo, uint64_t code_hi,
+                   uint32_t len_hi, const uint64_t* in_mask, uint64_t* out_bv, void* stream) {
+    if (!col) return set_error(BST_EINVAL, "NULL column");
+    if (col->dev.n && !out_bv) return set_error(BST_EINVAL, "NULL output bitvector");
+    ScanLit lit;
+    int rc = code_literal(*col->host, op, code_lo, len_lo, code_hi, len_hi, &lit);
+    if (rc) return rc;
+    if (lit.mode == kModeBetween && lit.lo > lit.hi) lit.mode = kModeNone;
+    return run_scan(col, lit, in_mask, out_bv, nullptr, (hipStream_t)stream);
+}
+
+int bst_scan_stats(const bst_column* col, bst_pred pred, const uint64_t* in_mask, uint64_t* out_bv,
+                   uint64_t* dev_counters, void* stream) {
+    if (!col || !dev_counters) return set_error(BST_EINVAL, "NULL argument");
+    if (col->dev.n && !out_bv) return set_error(BST_EINVAL, "NULL output bitvector");
+    ScanLit lit;
+    int rc = rewrite_predicate(*col->host, pred, &lit);
+    if (rc) return rc;
+    return run_scan(col, lit, in_mask, out_bv, (unsigned long long*)dev_counters, (hipStream_t)stream);
+}
+
+int bst_lookup(const bst_column* col, const uint32_t* row_ids, uint64_t m, uint32_t* out_values,
+               uint32_t* dev_status, void* stream) {
+    if (!col) return set_error(BST_EINVAL, "NULL column");
+    if (m == 0) return BST_OK;
+    if (!row_ids || !out_values) return set_error(BST_EINVAL, "NULL argument");
+    if (col->host->codes_only) return set_error(BST_EUNSUPPORTED, "lookup on a column built from explicit codes");
+    const uint32_t grid = g_tune[BST_TUNE_LOOKUP_GRID] > 0 ? (uint32_t)g_tune[BST_TUNE_LOOKUP_GRID] : elem_grid(m);
+    hipLaunchKernelGGL(k_lookup, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, col->dev, row_ids, m,
+                       (const unsigned long long*)nullptr, m, out_values, dev_status);
+    return hip_check(hipGetLastError(), "lookup launch");
+}
+
+uint64_t bst_compact_workspace_bytes(uint64_t n_rows) {
+    const uint64_t nt = (n_rows + kTileRows - 1) / kTileRows;
+    return 8 * (2 * nt + 2);
+}
+
+int bst_bv_compact(const uint64_t* bv, uint64_t n_rows, uint32_t* out_ids, uint64_t cap, uint64_t* dev_count,
+                   void* workspace, uint32_t* dev_status, void* stream) {
+    if (!dev_count || !workspace || (n_rows && !bv) || (cap && !out_ids)) return set_error(BST_EINVAL, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t nt = (n_rows + kTileRows - 1) / kTileRows;
+    uint64_t* counts = (uint64_t*)workspace;
+    uint64_t* offsets = counts + nt;
+    if (nt == 0) {
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, (unsigned long long*)dev_count, 1);
+        return hip_check(hipGetLastError(), "compact launch");
+    }
+    hipLaunchKernelGGL(k_tile_popc, dim3(tile_grid(nt, 0)), dim3(kBlock), 0, st, bv, n_rows, counts, nt);
+    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, st, counts, nt, offsets,
+                       (unsigned long long*)dev_count);
+    hipLaunchKernelGGL(k_write_ids, dim3(tile_grid(nt, 0)), dim3(kBlock), 0, st, bv, n_rows, offsets, nt, out_ids, cap,
+                       dev_status);
+    return hip_check(hipGetLastError(), "compact launch");
+}
+
+int bst_lookup_bv(const bst_column* col, const uint64_t* bv, uint32_t* out_values, uint64_t cap, uint64_t* dev_count,
+                  uint32_t* ids_tmp, void* workspace, uint32_t* dev_status, void* stream) {
+    if (!col) return set_error(BST_EINVAL, "NULL column");
+    if (col->host->codes_only) return set_error(BST_EUNSUPPORTED, "lookup on a column built from explicit codes");
+    int rc = bst_bv_compact(bv, col->dev.n, ids_tmp, cap, dev_count, workspace, dev_status, stream);
+    if (rc) return rc;
+    if (cap == 0) return BST_OK;
+    if (!out_values) return set_error(BST_EINVAL, "NULL output");
+    const uint32_t grid = g_tune[BST_TUNE_LOOKUP_GRID] > 0 ? (uint32_t)g_tune[BST_TUNE_LOOKUP_GRID] : elem_grid(cap);
+    hipLaunchKernelGGL(k_lookup, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, col->dev, ids_tmp, cap,
+                       (const unsigned long long*)dev_count, cap, out_values, dev_status);
+    return hip_check(hipGetLastError(), "lookup launch");
+}
+
+int bst_bv_and(const uint64_t* a, const uint64_t* b, uint64_t* out, uint64_t n_rows, void* stream) {
+    if (n_rows == 0) return BST_OK;
+    if (!a || !b || !out) return set_error(BST_EINVAL, "NULL argument");
+    hipLaunchKernelGGL(k_bv_binop, dim3(elem_grid((n_rows + 63) / 64)), dim3(kBlock), 0, (hipStream_t)stream, a, b, out,
+                       n_rows, 0);
+    return hip_check(hipGetLastError(), "bv_and launch");
+}
+
+int bst_bv_or(const uint64_t* a, const uint64_t* b, uint64_t* out, uint64_t n_rows, void* stream) {
+    if (n_rows == 0) return BST_OK;
+    if (!a || !b || !out) return set_error(BST_EINVAL, "NULL argument");
+    hipLaunchKernelGGL(k_bv_binop, dim3(elem_grid((n_rows + 63) / 64)), dim3(kBlock), 0, (hipStream_t)stream, a, b, out,
+                       n_rows, 1);
+    return hip_check(hipGetLastError(), "bv_or launch");
+}
+
+int bst_bv_popcount(const uint64_t* bv, uint64_t n_rows, uint64_t* dev_count, void* stream) {
+    if (!dev_count || (n_rows && !bv)) return set_error(BST_EINVAL, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, (unsigned long long*)dev_count, 1);
+    if (n_rows)
+        hipLaunchKernelGGL(k_bv_popcount, dim3(elem_grid((n_rows + 63) / 64)), dim3(kBlock), 0, st, bv, n_rows,
+                           (unsigned long long*)dev_count);
+    return hip_check(hipGetLastError(), "popcount launch");
+}
+
+// ---- advisor -------------------------------------------------------------
+int bst_advise(const bst_column* const* cands, int n_cand, int op, const uint32_t* lits, const double* sels, int n_lit,
+               int repeats, uint64_t* scratch_bv, double* times_out, double* auc_out, int* chosen, void* stream) {
+    if (!cands || n_cand < 1 || !lits || !sels || n_lit < 1 || !scratch_bv || !auc_out || !chosen)
+        return set_error(BST_EINVAL, "bad argument");
+    if (op != BST_LT && op != BST_EQ) return set_error(BST_EINVAL, "profiling op must be BST_LT or BST_EQ");
+    if (repeats < 1) repeats = 1;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    int rc = hip_check(hipEventCreate(&e0), "event");
+    if (rc) return rc;
+    rc = hip_check(hipEventCreate(&e1), "event");
+    if (rc) {
+        hipEventDestroy(e0);
+        return rc;
+    }
+    std::vector<int> layouts(n_cand);
+    std::vector<double> t(n_lit), samples(repeats);
+    for (int ci = 0; ci < n_cand && !rc; ++ci) {
+        const bst_column* col = cands[ci];
+        if (!col) { rc = set_error(BST_EINVAL, "NULL candidate"); break; }
+        layouts[ci] = (int)col->dev.layout;
+        for (int li = 0; li < n_lit && !rc; ++li) {
+            bst_pred p{op, lits[li], lits[li]};
+            ScanLit lit;
+            rc = rewrite_predicate(*col->host, p, &lit);
+            if (rc) break;
+            rc = run_scan(col, lit, nullptr, scratch_bv, nullptr, st);   // warm-up
+            for (int r = 0; r < repeats && !rc; ++r) {
+                hipEventRecord(e0, st);
+                rc = run_scan(col, lit, nullptr, scratch_bv, nullptr, st);
+                hipEventRecord(e1, st);
+                if (!rc) rc = hip_check(hipEventSynchronize(e1), "event sync");
+                float ms = 0;
+                if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+                samples[r] = ms * 1000.0;
+            }
+            if (rc) break;
+            std::sort(samples.begin(), samples.end());
+            t[li] = samples[repeats / 2];
+            if (times_out) times_out[(size_t)ci * n_lit + li] = t[li];
+        }
+        if (!rc) rc = bst_auc(sels, t.data(), n_lit, &auc_out[ci]);
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    return bst_choose(layouts.data(), auc_out, n_cand, chosen);
+}
+
+int bst_tune_set(int key, int64_t value) {
+    if (key < 0 || key >= BST_TUNE_NKEYS) return set_error(BST_EINVAL, "bad tuning key");
+    g_tune[key] = value;
+    return BST_OK;
+}
+
+int64_t bst_tune_get(int key) {
+    if (key < 0 || key >= BST_TUNE_NKEYS) return -1;
+    return g_tune[key];
+}
+
+}  // extern "C"
+

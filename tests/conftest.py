@@ -21,3 +21,15 @@ def golden():
 
     with open(os.path.join(GOLDEN, "paper_examples.json")) as f:
         return json.load(f)
+
+
+@pytest.fixture(scope="session")
+def built_lib():
+    """Path of libbytestore.so, building it (and the generator) when absent."""
+    from paper_2209_00220_amd import build as b
+
+    if not os.path.exists(b.LIB):
+        import __graft_entry__
+
+        __graft_entry__.build()
+    return b.LIB

@@ -1,0 +1,34 @@
+"""The C-ABI library loads on a CPU-only host and exports every declared symbol."""
+import ctypes
+import os
+import re
+
+from conftest import ROOT
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "bytestore.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bst_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(built_lib):
+    names = _declared()
+    assert len(names) >= 30
+    L = ctypes.CDLL(built_lib)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header(built_lib):
+    from paper_2209_00220_amd import _lib
+
+    assert set(_declared()) == set(_lib.exported_names())
+
+
+def test_library_loads_without_gpu(built_lib):
+    from paper_2209_00220_amd import _lib
+
+    assert _lib.bst_version() >= 10000
+    assert _lib.bst_device_count() >= 0
+    assert _lib.bst_tune_get(99) == -1

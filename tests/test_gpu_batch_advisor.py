@@ -1,0 +1,122 @@
+"""Batched scans (one persistent launch, optionally a HIP graph) equal per-query
+scans; the advisor's timing loop feeds Algorithm 5's choice."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+from helpers import close_columns, device_columns, flush
+from oracle import advisor as oadv
+from oracle.scan import scan_values_bv
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu(built_lib):
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _mixed_items(seed=0, n_cols=6):
+    rng = np.random.default_rng(seed)
+    cols, xs = [], []
+    for i in range(n_cols):
+        n = int(rng.integers(1, 400_000))
+        w = int(rng.integers(8, 33))
+        s = float(rng.uniform(0, 1.5))
+        x = datagen.zipf_column(n, w, s, seed=1000 + i)
+        xs.append((x, w))
+        cols.append(device_columns(x, w))
+    items = []
+    ops = ["lt", "le", "gt", "ge", "eq", "ne", "between"]
+    for k in range(40):
+        ci = int(rng.integers(0, n_cols))
+        lay = ["ppvbs", "byteslice", "bitpacked"][k % 3]
+        x, w = xs[ci]
+        op = ops[int(rng.integers(0, len(ops)))]
+        a, b = sorted(int(v) for v in x[rng.integers(0, x.shape[0], size=2)])
+        if rng.random() < 0.1:
+            a = int(rng.integers(0, 2 ** 32))
+        items.append((ci, lay, op, a, b))
+    return cols, xs, items
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_equals_single(use_graph):
+    from paper_2209_00220_amd import _lib
+    from paper_2209_00220_amd.batch import Batch
+    from paper_2209_00220_amd.column import bv_to_numpy
+
+    cols, xs, items = _mixed_items(seed=1 if use_graph else 0)
+    try:
+        outs, specs = [], []
+        for ci, lay, op, a, b in items:
+            dc = cols[ci][lay][1]
+            outs.append(dc.new_bv())
+            specs.append((dc, op, a, b if op == "between" else None, None))
+        # one item pipelines another's result
+        specs[5] = (specs[5][0], specs[5][1], specs[5][2], specs[5][3], None)
+        batch = Batch(specs, outs)
+        for rep in range(3):
+            for o in outs:
+                o.fill_(-1)
+            batch.launch(grid=0, tiles_per_grab=2, use_graph=use_graph)
+            torch.cuda.synchronize()
+            for (ci, lay, op, a, b), o in zip(items, outs):
+                x, w = xs[ci]
+                want = scan_values_bv(x, op, a, b if op == "between" else None)
+                assert np.array_equal(bv_to_numpy(o), want), (rep, lay, op, a, b)
+            # eager work between graph replays
+            _ = cols[0]["ppvbs"][1].scan("lt", 5)
+            torch.cuda.synchronize()
+        batch.close()
+    finally:
+        for c in cols:
+            close_columns(c)
+
+
+def test_batch_with_in_masks():
+    from paper_2209_00220_amd.batch import Batch
+    from paper_2209_00220_amd.column import bv_from_numpy, bv_to_numpy
+    from oracle.layout import unpack_bits
+
+    n = 250_001
+    x = datagen.zipf_column(n, 20, 1.0, seed=8)
+    cols = device_columns(x, 20)
+    mask = datagen.random_mask_words(n, seed=9, density=0.05)
+    mt = bv_from_numpy(mask)
+    try:
+        specs, outs = [], []
+        for lay in ("ppvbs", "byteslice", "bitpacked"):
+            for op, lo, hi in (("lt", 70_000, None), ("between", 5, 500_000), ("eq", int(x[10]), None)):
+                specs.append((cols[lay][1], op, lo, hi, mt))
+                outs.append(cols[lay][1].new_bv())
+        b = Batch(specs, outs)
+        b.launch(use_graph=True)
+        torch.cuda.synchronize()
+        rows = unpack_bits(mask, n)
+        for (dc, op, lo, hi, _), o in zip(specs, outs):
+            assert np.array_equal(bv_to_numpy(o), scan_values_bv(x, op, lo, hi, rows))
+        b.close()
+    finally:
+        close_columns(cols)
+
+
+def test_advisor_choice_consistent_with_oracle():
+    from paper_2209_00220_amd.advisor import advise_column
+
+    flush("advisor")
+    n = 2_000_000
+    x = datagen.zipf_column(n, 16, 1.5, seed=31)
+    res = advise_column(x, numeric=True, width=16, repeats=3, count=20)
+    # the product's area and choice are Algorithm 5's on its own measured times
+    for lay, t in res.times.items():
+        assert res.aucs[lay] == pytest.approx(oadv.auc(res.sels, t), rel=1e-9)
+    want = oadv.choose({oadv.BITPACKED if k == "bitpacked" else oadv.BYTESLICE if k == "byteslice" else oadv.PPVBS: v
+                        for k, v in res.aucs.items()})
+    name = {oadv.BITPACKED: "bitpacked", oadv.BYTESLICE: "byteslice", oadv.PPVBS: "ppvbs"}[want]
+    assert res.chosen == name
+    assert all(np.all(t > 0) for t in res.times.values())

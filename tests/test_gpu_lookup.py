@@ -1,0 +1,120 @@
+"""GPU lookups, compaction and bitvector helpers against the oracle (Sec. 2.2, 3.3)."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+from helpers import close_columns, device_columns, flush
+from oracle.layout import pack_bits, unpack_bits
+from oracle.lookup import bv_row_ids, lookup_bv, lookup_ids
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu(built_lib):
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _np32(t):
+    from paper_2209_00220_amd.column import u32_to_numpy
+
+    torch.cuda.synchronize()
+    return u32_to_numpy(t)
+
+
+@pytest.mark.parametrize("n,w,s,mapping", [
+    (1, 12, 1.0, datagen.SCATTER), (65, 12, 1.0, datagen.SCATTER), (4097, 20, 1.0, datagen.SORTED),
+    (300_007, 20, 1.0, datagen.SCATTER), (2_000_003, 20, 0.5, datagen.SORTED), (200_000, 32, 0.0, datagen.SCATTER),
+    (100_000, 8, 1.5, datagen.SCATTER),
+])
+def test_lookup_identity(n, w, s, mapping):
+    flush("lookup n=%d w=%d s=%g" % (n, w, s))
+    from paper_2209_00220_amd.column import u32_from_numpy
+
+    x = datagen.zipf_column(n, w, s, seed=n ^ w, mapping=mapping)
+    ids = np.concatenate([datagen.uniform_ids(20_000, n, seed=n), np.array([0, n - 1], dtype=np.uint32)])
+    for domain in (True, False):
+        cols = device_columns(x, w, domain=domain)
+        try:
+            for lay, (hc, col) in cols.items():
+                got = _np32(col.lookup(u32_from_numpy(ids)))
+                assert np.array_equal(got, lookup_ids(x, ids)), (lay, domain)
+                # every row in order
+                if n <= 300_007:
+                    allv = _np32(col.lookup(u32_from_numpy(np.arange(n, dtype=np.uint32))))
+                    assert np.array_equal(allv, x), (lay, domain)
+        finally:
+            close_columns(cols)
+
+
+def test_bad_row_sets_status():
+    from paper_2209_00220_amd.column import u32_from_numpy
+
+    n = 1000
+    x = datagen.zipf_column(n, 12, 1.0, seed=1)
+    cols = device_columns(x, 12)
+    try:
+        for lay, (hc, col) in cols.items():
+            status = torch.zeros(1, dtype=torch.int32, device="cuda")
+            ids = np.array([3, n, 5, 0xFFFFFFFF], dtype=np.uint32)
+            got = _np32(col.lookup(u32_from_numpy(ids), status=status))
+            assert list(got) == [x[3], 0, x[5], 0]
+            assert int(status.item()) & 1
+    finally:
+        close_columns(cols)
+
+
+@pytest.mark.parametrize("n,density", [(1, 1.0), (64, 0.5), (2049, 0.01), (1_000_003, 0.2), (1_000_003, 0.0)])
+def test_compact_and_lookup_bv(n, density):
+    from paper_2209_00220_amd.column import bv_compact, bv_from_numpy
+
+    x = datagen.zipf_column(n, 16, 1.0, seed=n)
+    R = datagen.random_mask_words(n, seed=n + 3, density=density)
+    Rt = bv_from_numpy(R)
+    want_ids = bv_row_ids(R, n)
+    cap = max(1, want_ids.shape[0])
+    ids, count = bv_compact(Rt, n, cap)
+    torch.cuda.synchronize()
+    assert int(count.item()) == want_ids.shape[0]
+    assert np.array_equal(_np32(ids)[: want_ids.shape[0]], want_ids)
+    cols = device_columns(x, 16)
+    try:
+        for lay, (hc, col) in cols.items():
+            vals, cnt = col.lookup_bv(Rt, cap)
+            torch.cuda.synchronize()
+            k = int(cnt.item())
+            assert k == want_ids.shape[0]
+            assert np.array_equal(_np32(vals)[:k], lookup_bv(x, R, n)), lay
+    finally:
+        close_columns(cols)
+
+
+def test_compact_overflow_flag():
+    from paper_2209_00220_amd.column import bv_compact, bv_from_numpy
+
+    n = 10_000
+    R = datagen.random_mask_words(n, seed=5, density=0.5)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ids, count = bv_compact(bv_from_numpy(R), n, 100, status=status)
+    torch.cuda.synchronize()
+    want = bv_row_ids(R, n)
+    assert int(count.item()) == want.shape[0]
+    assert np.array_equal(_np32(ids)[:100], want[:100])
+    assert int(status.item()) & 2
+
+
+def test_bitvector_helpers():
+    from paper_2209_00220_amd.column import bv_and, bv_from_numpy, bv_or, bv_popcount, bv_to_numpy
+
+    n = 123_457
+    a = datagen.random_mask_words(n, seed=1, density=0.3)
+    b = datagen.random_mask_words(n, seed=2, density=0.6)
+    ta, tb = bv_from_numpy(a), bv_from_numpy(b)
+    ra, rb = unpack_bits(a, n), unpack_bits(b, n)
+    assert np.array_equal(bv_to_numpy(bv_and(ta, tb, n)), pack_bits(ra & rb))
+    assert np.array_equal(bv_to_numpy(bv_or(ta, tb, n)), pack_bits(ra | rb))
+    assert int(bv_popcount(ta, n).item()) == int(ra.sum())
