@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Scan / lookup benchmark on one MI355X.
+
+Workload (one step = the whole hot path over one synthetic column):
+  one column of 500M rows, Zipf(1.0) over 2^20 values (20-bit codes), stored as
+  PP-VBS, ByteSlice (3 slices) and Bit-Packed (20 bits); on each layout the
+  scans '<', '=' and BETWEEN at selectivities 0.1, 1, 10, 50, 90 % into a
+  result bitvector, then a lookup of 5M uniform random row IDs (1 %) returning
+  uint32 values.
+
+Printed: one JSON line.  ``value`` is the PP-VBS scan throughput in Gtuples/s
+(rows scanned / kernel time, inputs resident in HBM); the line also carries
+ByteSlice / Bit-Packed scan and lookup throughputs, the roofline of the PP-VBS
+scan kernel (algorithmic bytes per launch over its HIP-event duration against
+8 TB/s) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "scan Gtuples/s + % HBM peak (PP-VBS vs ByteSlice); lookup Mrows/s; p99"
+HBM_PEAK_GBS = 8000.0
+LAYOUTS = ("ppvbs", "byteslice", "bitpacked")
+KERNEL_SOURCES = ("paper_2209_00220_amd/csrc/device_common.h", "paper_2209_00220_amd/csrc/scan_kernel.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ppvbs_scan_500M_traffic.txt")
+
+
+def progress(msg: str):
+    sys.stderr.write("[bench %7.1fs] %s\n" % (time.time() - T0, msg))
+    sys.stderr.flush()
+
+
+T0 = time.time()
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per PP-VBS scan launch from the committed rocprofv3 counter summary,
+    only when it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_hash") != kernel_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(x, preds, sample_rows: int):
+    """The oracle (decode every code, compare, pack bits) on the first sample_rows rows."""
+    import numpy as np
+
+    from oracle.dictionary import build_dictionary
+    from oracle.layout import vbs_build
+    from oracle.ppe import ppe_numerical
+    from oracle.scan import CodeTable, scan_vbs
+
+    xs = np.ascontiguousarray(x[:sample_rows])
+    A, Q, rank = build_dictionary(xs)
+    C, Lc = ppe_numerical(Q)
+    K = int(Lc.max())
+    BS, M = vbs_build(C[rank], Lc[rank], K)
+    table = CodeTable(A, C, Lc, K)
+    t0 = time.perf_counter()
+    for op, lo, hi, _ in preds:
+        scan_vbs(BS, M, K, table, op, lo, hi)
+    dt = time.perf_counter() - t0
+    return {
+        "value": round(sample_rows * len(preds) / dt / 1e9, 6),
+        "unit": "Gtuples/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "PP-VBS scans (decode, compare, pack) of the first %d rows of the same column, "
+                  "the same %d predicates, numpy on one host thread, %.1f s" % (sample_rows, len(preds), dt),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--rows", type=int, default=500_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=4_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--layouts", default=",".join(LAYOUTS))
+    ap.add_argument("--no-lookup", action="store_true")
+    ap.add_argument("--preds", default="", help="comma-separated predicate indices to run (profiling)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device-to-device (a plain copy kernel to scale memory counters)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the scan/lookup path has no multi-GPU form here "
+              "(rows would shard by range with no exchange); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from datagen import workloads
+    from paper_2209_00220_amd import _lib
+    from paper_2209_00220_amd.column import DeviceColumn, Dictionary, HostColumn, u32_from_numpy
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    layouts = [l for l in args.layouts.split(",") if l]
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    n = args.rows
+    progress("generating %d rows (Zipf 1.0 over 2^20)" % n)
+    wl = workloads.config2(n)
+    x, preds, ids = wl["x"], wl["preds"], wl["ids"]
+    if args.preds:
+        preds = [preds[int(i)] for i in args.preds.split(",")]
+    progress("dictionary")
+    d = Dictionary(x)
+    cols = {}
+    for lay in layouts:
+        progress("encode + upload %s" % lay)
+        hc = HostColumn.encode(d, lay, width=0 if lay == "ppvbs" else 20)
+        cols[lay] = (hc, DeviceColumn(hc))
+    d.close()
+    torch.cuda.synchronize()
+    ids_t = u32_from_numpy(ids)
+    out_bv = cols[layouts[0]][1].new_bv()
+    out_vals = torch.empty(ids.shape[0], dtype=torch.int32, device="cuda")
+
+    # algorithmic bytes per scan launch (deterministic per predicate), untimed
+    alg = {}
+    for lay in layouts:
+        col = cols[lay][1]
+        for i, (op, lo, hi, _) in enumerate(preds):
+            _, ctr = col.scan_stats(op, lo, hi, out=out_bv)
+            torch.cuda.synchronize()
+            c = ctr.cpu().numpy()
+            alg[(lay, i)] = (int(c[0]), int(c[3]))
+    progress("counters done")
+
+    stream = torch.cuda.current_stream()
+    n_ev = len(layouts) * (len(preds) + 1)
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_ev)]
+
+    def step():
+        e = 0
+        for lay in layouts:
+            col = cols[lay][1]
+            for op, lo, hi, _ in preds:
+                events[e][0].record(stream)
+                col.scan(op, lo, hi, out=out_bv)
+                events[e][1].record(stream)
+                e += 1
+            events[e][0].record(stream)
+            if not args.no_lookup:
+                col.lookup(ids_t, out=out_vals)
+            events[e][1].record(stream)
+            e += 1
+
+    def durations():
+        torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in events]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    progress("warmup done; timing %d steps" % args.steps)
+    acc = np.zeros(n_ev)
+    t_total = 0.0
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        t_total += time.perf_counter() - t0
+        acc += np.asarray(durations())
+    dur = acc / args.steps   # ms per launch, averaged over steps
+    ms_per_step = t_total / args.steps * 1e3
+
+    res = {}
+    e = 0
+    for lay in layouts:
+        scan_ms = dur[e:e + len(preds)]
+        alg_b = np.array([alg[(lay, i)][0] for i in range(len(preds))], dtype=np.float64)
+        full_b = np.array([alg[(lay, i)][1] for i in range(len(preds))], dtype=np.float64)
+        res[lay] = {
+            "scan_gtuples": n * len(preds) / (scan_ms.sum() * 1e-3) / 1e9,
+            "scan_ms": scan_ms.tolist(),
+            "alg_gbs": alg_b.sum() / (scan_ms.sum() * 1e-3) / 1e9,
+            "alg_bytes_per_launch": float(alg_b.mean()),
+            "full_bytes_per_launch": float(full_b.mean()),
+            "lookup_ms": float(dur[e + len(preds)]),
+            "lookup_mrows": (ids.shape[0] / (dur[e + len(preds)] * 1e-3) / 1e6) if not args.no_lookup else None,
+        }
+        e += len(preds) + 1
+
+    main_lay = "ppvbs" if "ppvbs" in res else layouts[0]
+    r = res[main_lay]
+    traffic = read_traffic()
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(r["alg_gbs"], 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(r["alg_gbs"] / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "kernel": "k_scan_slices (PP-VBS)",
+        "alg_bytes_per_launch": r["alg_bytes_per_launch"],
+        "avg_launch_ms": float(np.mean(r["scan_ms"])),
+    }
+    out = {
+        "metric": METRIC,
+        "value": round(r["scan_gtuples"], 3),
+        "unit": "Gtuples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": "1 column x %d rows, 20-bit Zipf(1.0) values; PP-VBS / ByteSlice / Bit-Packed; "
+                        "<, =, BETWEEN at 0.1/1/10/50/90%% selectivity; lookup of %d random row IDs" % (n, ids.shape[0]),
+            "rows": n,
+            "predicates": [[op, lo, hi, round(sel, 6)] for op, lo, hi, sel in preds],
+            "lookup_ids": int(ids.shape[0]),
+            "layout_bytes": {lay: int(cols[lay][0].info.layout_bytes) for lay in layouts},
+        },
+        "roofline": roofline,
+        "layouts": {lay: {
+            "scan_gtuples": round(v["scan_gtuples"], 3),
+            "scan_hbm_frac": round(v["alg_gbs"] / HBM_PEAK_GBS, 4),
+            "alg_bytes_per_launch": round(v["alg_bytes_per_launch"]),
+            "full_bytes_per_launch": round(v["full_bytes_per_launch"]),
+            "lookup_mrows": None if v["lookup_mrows"] is None else round(v["lookup_mrows"], 1),
+        } for lay, v in res.items()},
+        "lookup_mrows": None if r["lookup_mrows"] is None else round(r["lookup_mrows"], 1),
+        "p99_ms": None,
+    }
+    for lay in layouts:
+        progress("%-9s scan %.1f Gtuples/s  (%.0f GB/s algorithmic, %.1f%% of 8 TB/s)  lookup %s Mrows/s" % (
+            lay, res[lay]["scan_gtuples"], res[lay]["alg_gbs"], 100 * res[lay]["alg_gbs"] / HBM_PEAK_GBS,
+            "-" if res[lay]["lookup_mrows"] is None else "%.0f" % res[lay]["lookup_mrows"]))
+    if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle) on %d rows" % args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(x, preds, min(args.cpu_sample, n))
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,89 @@
+"""Synthetic workloads: value columns, predicate literals at target selectivities,
+and row-ID lists.  Literals are picked from the value counts of the generated
+column (plain quantiles); nothing here encodes or scans.
+
+Workloads
+---------
+config1: one column of 1M rows, Zipf(1.0) over 4096 values (12-bit), seed 0;
+         '<' at about 10 %, 10k uniform row IDs.
+config2: one column of 500M rows, Zipf(1.0) over 2^20 values (20-bit); '<', '='
+         and BETWEEN at selectivities 0.1, 1, 10, 50, 90 % ('=' cannot exceed
+         the largest value frequency, about 6.9 %, and takes the nearest one);
+         5M uniform row IDs (1 %), seed 1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import uniform_ids, zipf_column
+
+SELECTIVITIES = (0.001, 0.01, 0.10, 0.50, 0.90)
+
+
+def value_counts(x: np.ndarray, w: int):
+    """(values, counts) of the distinct values, ascending."""
+    if w <= 26:
+        c = np.bincount(x, minlength=1 << w)
+        v = np.nonzero(c)[0]
+        return v.astype(np.uint32), c[v].astype(np.int64)
+    v, c = np.unique(x, return_counts=True)
+    return v.astype(np.uint32), c.astype(np.int64)
+
+
+def lit_lt(values, counts, target: float):
+    """Literal c with fraction of rows below c nearest target; returns (c, selectivity)."""
+    n = counts.sum()
+    below = np.concatenate([[0], np.cumsum(counts)[:-1]]) / n
+    k = int(np.argmin(np.abs(below - target)))
+    return int(values[k]), float(below[k])
+
+
+def lit_eq(values, counts, target: float):
+    """Value whose frequency is nearest target; returns (value, selectivity)."""
+    n = counts.sum()
+    f = counts / n
+    k = int(np.argmin(np.abs(f - target)))
+    return int(values[k]), float(f[k])
+
+
+def lit_between(values, counts, target: float):
+    """Centred range [q((1-s)/2), q((1+s)/2)]; returns (lo, hi, selectivity)."""
+    n = counts.sum()
+    cum = np.cumsum(counts) / n
+    lo_k = int(np.searchsorted(cum, (1.0 - target) / 2.0, side="left"))
+    hi_k = int(np.searchsorted(cum, (1.0 + target) / 2.0, side="left"))
+    lo_k = min(lo_k, len(values) - 1)
+    hi_k = min(max(hi_k, lo_k), len(values) - 1)
+    sel = float(cum[hi_k] - (cum[lo_k - 1] if lo_k > 0 else 0.0))
+    return int(values[lo_k]), int(values[hi_k]), sel
+
+
+def predicate_set(x: np.ndarray, w: int, selectivities=SELECTIVITIES):
+    """[(op, lo, hi, selectivity)] for '<', '=' and BETWEEN at each target."""
+    v, c = value_counts(x, w)
+    preds = []
+    for s in selectivities:
+        lo, sel = lit_lt(v, c, s)
+        preds.append(("lt", lo, None, sel))
+    for s in selectivities:
+        lo, sel = lit_eq(v, c, s)
+        preds.append(("eq", lo, None, sel))
+    for s in selectivities:
+        lo, hi, sel = lit_between(v, c, s)
+        preds.append(("between", lo, hi, sel))
+    return preds
+
+
+def config1(threads=None):
+    x = zipf_column(1_000_000, 12, 1.0, seed=0, threads=threads)
+    v, c = value_counts(x, 12)
+    lit, sel = lit_lt(v, c, 0.10)
+    return {"x": x, "w": 12, "lt_literal": lit, "lt_selectivity": sel, "ids": uniform_ids(10_000, x.shape[0], seed=0)}
+
+
+def config2(n: int = 500_000_000, threads=None, n_ids: int | None = None):
+    x = zipf_column(n, 20, 1.0, seed=2, threads=threads)
+    preds = predicate_set(x, 20)
+    m = n_ids if n_ids is not None else max(1, n // 100)
+    ids = uniform_ids(m, n, seed=1)
+    return {"x": x, "w": 20, "preds": preds, "ids": ids}

@@ -30,6 +30,7 @@ namespace dev {
 
 constexpr int kBlock = 256;           // threads per workgroup: 4 waves
 constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kMinWaves = 6;            // waves per SIMD the scan kernels are built for
 
 // ------------------------------------------------------------ wave helpers
 __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
@@ -39,12 +40,19 @@ __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// v_writelane_b32: lane LANE of the VGPR takes the uniform value v (an SGPR)
-template <int LANE>
-__device__ __forceinline__ uint32_t put_lane(uint32_t old, uint32_t v) {
+// Lanes 2K and 2K+1 of v take the uniform values lo and hi (v_writelane_b32 with
+// SGPR data).  The values usually come straight from a VALU compare or
+// readfirstlane, and a VALU read of an SGPR that a VALU instruction just wrote
+// needs two wait states on this chip; the compiler cannot see into the asm, so
+// the s_nop that provides them is part of it.
+template <int K>
+__device__ __forceinline__ uint32_t put_word(uint32_t v, uint32_t lo, uint32_t hi) {
     uint32_t r;
-    const uint32_t s = __builtin_amdgcn_readfirstlane(v);
-    asm("v_writelane_b32 %0, %1, %2" : "=v"(r) : "s"(s), "i"(LANE), "0"(old));
+    const uint32_t slo = __builtin_amdgcn_readfirstlane(lo);
+    const uint32_t shi = __builtin_amdgcn_readfirstlane(hi);
+    asm volatile("s_nop 1\n\tv_writelane_b32 %0, %1, %3\n\tv_writelane_b32 %0, %2, %4"
+                 : "=v"(r)
+                 : "s"(slo), "s"(shi), "i"(2 * K), "i"(2 * K + 1), "0"(v));
     return r;
 }
 
@@ -93,134 +101,104 @@ __device__ __forceinline__ uint64_t vbs_group_base(const DevCol& c, uint32_t j, 
 }
 
 // ------------------------------------------------------------ slice scan
-// Classify one 64-row group against a literal byte by byte (Sec. 3.3,
-// Algorithm 3 generalised to every operator).  A row stays pending while its
-// bytes equal the literal's; at byte j < l a pending row without a (j+1)-th
-// byte is a proper prefix of the literal, hence smaller (the literal's rest is
-// not all zero); at j = l a pending row is greater if it has byte l+1, else
-// equal.  Bytes are compared unsigned.  The group stops as soon as no row is
-// pending (a wave-uniform test), so later slices are only read for the rows
-// still undecided.
+// A tile of a slice-layout scan is one wave's work: 32 groups of 64 rows, each
+// group's result one uint64 word.  The comparison of a row against a literal
+// proceeds byte by byte (Sec. 3.3, Algorithm 3 generalised to every operator):
+// a row whose byte differs from the literal's is decided; a row still equal
+// after byte j stays pending, except that at j < l a row without a byte j+1 is
+// a proper prefix of the literal and hence smaller (the literal's remaining
+// bytes are not all zero), and at j = l a row with a byte l+1 is greater, one
+// without it equal.  Bytes compare unsigned.
 //
-// MODE kModeLT: returns rows with code < lit; kModeGT: code > lit;
-// kModeEQ: code == lit.  Rows outside `act` are never reported.
-template <int MODE, bool DENSE, bool COUNT>
-__device__ __forceinline__ uint64_t classify_one(const DevCol& c, uint64_t lit6, uint32_t l, uint32_t b1,
-                                                 uint64_t act, uint64_t g, uint32_t lane, Stats& st) {
-    uint32_t cb = lit_byte(lit6, 1);
-    uint64_t X = 0;
-    uint64_t P = ballot(b1 == cb) & act;
-    if (MODE == kModeLT) X = ballot(b1 < cb) & act;
-    if (MODE == kModeGT) X = ballot(b1 > cb) & act;
-    if (COUNT) st.rowbytes += __builtin_popcountll(act);
-    const uint32_t K = c.K;
-    bool deep = false;
-    for (uint32_t j = 1; P != 0; ++j) {
-        uint64_t mnext;
-        if (j >= K) {
-            mnext = 0;
-        } else if (DENSE) {
-            mnext = ~0ull;
-        } else {
-            mnext = c.m[j + 1][g];
-            if (COUNT) st.alg += 8;
-        }
-        if (j >= l) {
-            if (MODE == kModeGT) X |= P & mnext;
-            if (MODE == kModeEQ) X |= P & ~mnext;
-            break;
-        }
-        if (MODE == kModeLT) X |= P & ~mnext;
-        P &= mnext;
-        if (P == 0) break;
-        // byte j+1 of the pending rows
-        uint32_t bb = 0;
-        const bool mine = (P >> lane) & 1;
-        if (DENSE) {
-            if (mine) bb = c.bs[j + 1][(g << 6) + lane];
-            if (COUNT) st.alg += 64;
-        } else {
-            const uint64_t base = vbs_group_base(c, j + 1, g);
-            if (mine) bb = c.bs[j + 1][base + mbcnt(mnext)];
-            if (COUNT) st.alg += __builtin_popcountll(mnext);
-        }
-        if (COUNT) {
-            st.rowbytes += __builtin_popcountll(P);
-            deep = true;
-        }
-        cb = lit_byte(lit6, j + 1);
-        const uint64_t lt = ballot(bb < cb) & P;
-        const uint64_t gt = ballot(bb > cb) & P;
-        const uint64_t eq = ballot(bb == cb) & P;
-        if (MODE == kModeLT) X |= lt;
-        if (MODE == kModeGT) X |= gt;
-        (void)gt;
-        (void)lt;
-        P = eq;
+// Phase 1 compares byte 1 of all 32 groups (no memory wait, the tile is in
+// registers) and records the groups that still have pending rows.  Phase 2
+// settles only those groups: M_2 words come from the tile's prefetched mask
+// dwords, and the byte-2 gathers of up to four groups are issued before any of
+// them is waited on; deeper bytes, rarer still, are read group by group.  So
+// later slices are read only for groups whose rows are undecided -- the early
+// stop of Algorithm 3 at 64-row granularity, tested wave-uniformly.
+
+// Per-lane registers of one tile.
+struct TileData {
+    uint4 q0, q1;   // 32 first-slice bytes: byte k is row tile*2048 + 64k + lane
+    uint32_t m2;    // PP-VBS: dword `lane` of the tile's 32 M_2 words (0 when unused)
+    uint32_t in;    // dword `lane` of the tile's 32 incoming-mask words (all ones when none)
+};
+
+template <bool DENSE, bool HAS_IN>
+__device__ __forceinline__ TileData load_tile(const DevCol& c, const uint64_t* __restrict__ in_mask, uint64_t t,
+                                              uint32_t lane) {
+    TileData d;
+    const uint4* p = reinterpret_cast<const uint4*>(c.bs[1] + t * kTileRows) + lane * 2;
+    d.q0 = p[0];
+    d.q1 = p[1];
+    d.m2 = 0;
+    if (!DENSE && c.K >= 2) d.m2 = reinterpret_cast<const uint32_t*>(c.m[2])[t * 64 + lane];
+    d.in = ~0u;
+    if (HAS_IN) {
+        const uint64_t dd = t * 64 + lane;
+        d.in = dd < ((c.n + 63) >> 6) * 2 ? reinterpret_cast<const uint32_t*>(in_mask)[dd] : 0u;
     }
-    if (COUNT && deep) st.deep_groups += 1;
-    return X;
+    return d;
 }
 
-// BETWEEN: rows with lo <= code <= hi, both literals classified in one pass.
-template <bool DENSE, bool COUNT>
-__device__ __forceinline__ uint64_t classify_between(const DevCol& c, const ScanLit& lit, uint32_t b1,
-                                                     uint64_t act, uint64_t g, uint32_t lane, Stats& st) {
-    uint32_t clo = lit_byte(lit.lo, 1), chi = lit_byte(lit.hi, 1);
-    uint64_t below = ballot(b1 < clo) & act;   // code < lo
-    uint64_t above = ballot(b1 > chi) & act;   // code > hi
-    uint64_t Plo = ballot(b1 == clo) & act;
-    uint64_t Phi = ballot(b1 == chi) & act;
-    if (COUNT) st.rowbytes += __builtin_popcountll(act);
-    const uint32_t K = c.K;
-    bool deep = false;
-    for (uint32_t j = 1; (Plo | Phi) != 0; ++j) {
-        uint64_t mnext;
-        if (j >= K) {
-            mnext = 0;
-        } else if (DENSE) {
-            mnext = ~0ull;
-        } else {
-            mnext = c.m[j + 1][g];
-            if (COUNT) st.alg += 8;
-        }
-        if (j >= lit.llo) {
-            Plo = 0;   // equal to lo or longer: not below lo
-        } else {
-            below |= Plo & ~mnext;
-            Plo &= mnext;
-        }
-        if (j >= lit.lhi) {
-            above |= Phi & mnext;
-            Phi = 0;
-        } else {
-            Phi &= mnext;   // a proper prefix of hi is below hi
-        }
-        const uint64_t P = Plo | Phi;
-        if (P == 0) break;
-        uint32_t bb = 0;
-        const bool mine = (P >> lane) & 1;
-        if (DENSE) {
-            if (mine) bb = c.bs[j + 1][(g << 6) + lane];
-            if (COUNT) st.alg += 64;
-        } else {
-            const uint64_t base = vbs_group_base(c, j + 1, g);
-            if (mine) bb = c.bs[j + 1][base + mbcnt(mnext)];
-            if (COUNT) st.alg += __builtin_popcountll(mnext);
-        }
-        if (COUNT) {
-            st.rowbytes += __builtin_popcountll(P);
-            deep = true;
-        }
-        clo = lit_byte(lit.lo, j + 1);
-        chi = lit_byte(lit.hi, j + 1);
-        below |= ballot(bb < clo) & Plo;
-        above |= ballot(bb > chi) & Phi;
-        Plo = ballot(bb == clo) & Plo;
-        Phi = ballot(bb == chi) & Phi;
+// 64-bit value held by lanes 2k (low half) and 2k+1 (high half) of v; k uniform.
+__device__ __forceinline__ uint64_t lane_word(uint32_t v, uint32_t k) {
+    return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)v, (int)(2 * k)) |
+           ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)v, (int)(2 * k + 1)) << 32);
+}
+
+// Store the uniform 64-bit value w into lanes 2k and 2k+1 of v; k uniform.
+__device__ __forceinline__ uint32_t set_lane_word(uint32_t v, uint32_t k, uint64_t w, uint32_t lane) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)w);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(w >> 32));
+    return lane == 2 * k ? lo : (lane == 2 * k + 1 ? hi : v);
+}
+
+// Rows equal to the literal on bytes 1..j meet m (rows that have a byte j+1):
+// settle what the lengths decide.  plo: pending against the (lower) literal,
+// phi: pending against the upper BETWEEN literal; hit: rows newly found in the
+// tracked relation (LT / GT / EQ; BETWEEN: below lo or above hi).  klo / khi are
+// all ones while j is shorter than the literal (j < l), else zero.
+template <int MODE>
+__device__ __forceinline__ void level_mask_step(uint64_t& plo, uint64_t& phi, uint64_t& hit, uint64_t m,
+                                                uint64_t klo, uint64_t khi) {
+    if (MODE == kModeLT || MODE == kModeBetween) {
+        hit |= plo & ~m & klo;       // a proper prefix of the literal is below it
+    } else if (MODE == kModeGT) {
+        hit |= plo & m & ~klo;       // equal over the literal's length, then more bytes: above
+    } else {
+        hit |= plo & ~m & ~klo;      // equal over the literal's length and no more bytes: equal
     }
-    if (COUNT && deep) st.deep_groups += 1;
-    return act & ~below & ~above;
+    plo &= m & klo;
+    if (MODE == kModeBetween) {
+        hit |= phi & m & ~khi;
+        phi &= m & khi;
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void level_step(uint64_t& plo, uint64_t& phi, uint64_t& hit, uint64_t m, uint32_t j,
+                                           uint32_t llo, uint32_t lhi) {
+    level_mask_step<MODE>(plo, phi, hit, m, j < llo ? ~0ull : 0ull, j < lhi ? ~0ull : 0ull);
+}
+
+// Compare byte j+1 (bb, valid in pending lanes) against the literal's byte.
+template <int MODE>
+__device__ __forceinline__ void byte_step(uint64_t& plo, uint64_t& phi, uint64_t& hit, uint32_t bb, uint32_t clo,
+                                          uint32_t chi) {
+    if (MODE == kModeLT || MODE == kModeBetween) hit |= ballot(bb < clo) & plo;
+    if (MODE == kModeGT) hit |= ballot(bb > clo) & plo;
+    if (MODE == kModeBetween) hit |= ballot(bb > chi) & phi;
+    plo &= ballot(bb == clo);
+    if (MODE == kModeBetween) phi &= ballot(bb == chi);
+}
+
+// Fold newly settled rows into a group's result word (kept un-negated until the
+// tile is stored: rows in the relation for '<', '>', '='; rows in range for BETWEEN).
+template <int MODE>
+__device__ __forceinline__ uint64_t apply_hit(uint64_t res, uint64_t hit) {
+    return MODE == kModeBetween ? (res & ~hit) : (res | hit);
 }
 
 // Bytes an exhaustive (no early stop) scan of this tile would touch.
@@ -240,53 +218,292 @@ __device__ uint64_t full_read_bytes(const DevCol& c, const ScanLit& lit, uint64_
     return bytes;
 }
 
-// One tile of a slice-layout scan, done by one wave.
-template <int MODE, bool DENSE, bool HAS_IN, bool COUNT>
-__device__ __forceinline__ void scan_slices_tile(const DevCol& c, const ScanLit& lit,
-                                                 const uint64_t* __restrict__ in_mask,
-                                                 uint64_t* __restrict__ out, uint64_t t, uint32_t lane,
-                                                 Stats& st) {
-    const uint64_t w0 = t * 32;
-    uint32_t* out32 = reinterpret_cast<uint32_t*>(out);
-    const uint64_t nwords = (c.n + 63) >> 6;
-    if (HAS_IN) {
-        // a tile whose incoming mask is all zero is not read at all
-        const uint64_t d = w0 * 2 + lane;
-        const uint32_t mine = d < nwords * 2 ? reinterpret_cast<const uint32_t*>(in_mask)[d] : 0u;
-        if (ballot(mine != 0) == 0) {
-            if (d < nwords * 2) out32[d] = 0;
-            if (COUNT) st.alg += 256 + 256;
-            return;
-        }
+// 64-bit word held by lanes 2K and 2K+1 of v, K a compile-time constant.
+template <int K>
+__device__ __forceinline__ uint64_t lane_word_c(uint32_t v) {
+    return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)v, 2 * K) |
+           ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)v, 2 * K + 1) << 32);
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t set_word_c(uint32_t v, uint64_t w) {
+    return put_word<K>(v, (uint32_t)w, (uint32_t)(w >> 32));
+}
+
+// Inclusive prefix sum over the wave's lanes.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v, uint32_t lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(v, o, 64);
+        if ((int)lane >= o) v += y;
     }
-    const uint4* p = reinterpret_cast<const uint4*>(c.bs[1] + t * kTileRows) + lane * 2;
-    const uint4 q0 = p[0], q1 = p[1];
-    const uint32_t dw[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+    return v;
+}
+
+constexpr uint32_t kStageBytes = 2080;   // 130 chunks of 16 bytes: a 2048-byte run plus alignment
+
+// Copy bytes [start, start+len) of a slice into this wave's LDS buffer with
+// 16-byte loads from the aligned-down start; returns start's offset in the buffer.
+__device__ __forceinline__ uint32_t stage_run(const uint8_t* __restrict__ src, uint64_t start, uint32_t len,
+                                              uint8_t* buf, uint32_t lane) {
+    const uint64_t a = start & ~15ull;
+    const uint64_t end = start + len;
+#pragma unroll
+    for (uint32_t i = lane; i < kStageBytes / 16; i += 64) {
+        const uint64_t p = a + 16ull * i;
+        if (p < end) *reinterpret_cast<uint4*>(buf + 16 * i) = *reinterpret_cast<const uint4*>(src + p);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return (uint32_t)(start - a);
+}
+
+// One tile, one wave, in two passes.
+//
+// Pass 1 walks the 32 groups (unrolled, first-slice bytes in registers) and
+// settles each group as deep as it can without waiting on memory: byte 1, the
+// presence of byte 2 (M_2, prefetched with the tile) and, when the launch
+// stages them, bytes 2 and 3 read from this wave's LDS copy of the tile's part
+// of BS_2 / BS_3 (one coalesced read each, made before the pass).  The host
+// stages a slice when many groups are expected to need it; otherwise pass 1
+// leaves those groups pending.
+//
+// Pass 2 finishes the pending groups byte by byte: with many of them it stages
+// the slice in LDS, with few it gathers just their bytes, four groups in
+// flight.  Pending rows and results live in VGPR lanes (2k, 2k+1) per group.
+template <int MODE, int SHORT, bool DENSE, bool HAS_IN, bool COUNT>
+__device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit, uint64_t* __restrict__ out,
+                                             uint64_t t, uint32_t lane, const TileData& td, uint8_t* lds,
+                                             Stats& st) {
+    const uint64_t w0 = t * 32;
+    const uint64_t nwords = (c.n + 63) >> 6;
+    const uint32_t K = c.K;
+    const uint32_t clo = lit_byte(lit.lo, 1), chi = lit_byte(lit.hi, 1);
+    const uint32_t c2lo = lit_byte(lit.lo, 2), c2hi = lit_byte(lit.hi, 2);
+    const uint32_t c3lo = lit_byte(lit.lo, 3), c3hi = lit_byte(lit.hi, 3);
+    const bool negate = lit.negate != 0;
+    const uint32_t dw[8] = {td.q0.x, td.q0.y, td.q0.z, td.q0.w, td.q1.x, td.q1.y, td.q1.z, td.q1.w};
     if (COUNT) {
         st.alg += kTileRows + 256 + (HAS_IN ? 256 : 0);
         st.full += full_read_bytes<DENSE>(c, lit, t, HAS_IN);
     }
-    uint32_t outv = 0;
+    // slices staged for pass 1
+    const bool s2 = (lit.stage & 1) && K >= 2;
+    const bool s3 = s2 && (lit.stage & 2) && K >= 3;
+    uint32_t m3v = 0, incl2 = 0, incl3 = 0, sh2 = 0, sh3 = 0;
+    uint8_t* lds2 = lds;
+    uint8_t* lds3 = lds + kStageBytes;
+    if (s2) {
+        if (!DENSE && K >= 3) m3v = reinterpret_cast<const uint32_t*>(c.m[3])[t * 64 + lane];
+        if (DENSE) {
+            sh2 = stage_run(c.bs[2], t * kTileRows, kTileRows, lds2, lane);
+        } else {
+            incl2 = wave_incl_sum(__builtin_popcount(td.m2), lane);
+            sh2 = stage_run(c.bs[2], c.dir[2][(t * kTileRows) >> c.dir_shift],
+                            (uint32_t)__builtin_amdgcn_readlane((int)incl2, 63), lds2, lane);
+        }
+    }
+    if (s3) {
+        if (DENSE) {
+            sh3 = stage_run(c.bs[3], t * kTileRows, kTileRows, lds3, lane);
+        } else {
+            incl3 = wave_incl_sum(__builtin_popcount(m3v), lane);
+            sh3 = stage_run(c.bs[3], c.dir[3][(t * kTileRows) >> c.dir_shift],
+                            (uint32_t)__builtin_amdgcn_readlane((int)incl3, 63), lds3, lane);
+        }
+    }
+    uint32_t m4v = 0;
+    if (s3 && !DENSE && K >= 4) m4v = reinterpret_cast<const uint32_t*>(c.m[4])[t * 64 + lane];
+    // byte 1: SHORT bit 0 (bit 1) says the lower (upper) literal is one byte long
+    // (SHORT < 0: decided at run time)
+    const uint64_t k1lo = SHORT < 0 ? (1 < lit.llo ? ~0ull : 0ull) : ((SHORT & 1) ? 0ull : ~0ull);
+    const uint64_t k1hi = SHORT < 0 ? (1 < lit.lhi ? ~0ull : 0ull) : ((SHORT & 2) ? 0ull : ~0ull);
+    // PP-VBS mask dwords are zero past the longest code; ByteSlice rows have all K bytes
+    const uint64_t has2 = K >= 2 ? ~0ull : 0ull, has3 = K >= 3 ? ~0ull : 0ull, has4 = K >= 4 ? ~0ull : 0ull;
+    uint32_t outv = 0, plov = 0, phiv = 0, pend = 0;
     Unroll<0, 32>::run([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        const uint64_t g = w0 + k;
-        uint64_t act = valid_mask(g, c.n);
-        if (HAS_IN) act &= (g < nwords) ? in_mask[g] : 0ull;
-        uint64_t res = 0;
-        if (act != 0) {
-            const uint32_t b1 = (dw[k >> 2] >> (8 * (k & 3))) & 0xffu;
-            if (MODE == kModeBetween) {
-                res = classify_between<DENSE, COUNT>(c, lit, b1, act, g, lane, st);
-            } else {
-                const uint64_t X = classify_one<MODE, DENSE, COUNT>(c, lit.lo, lit.llo, b1, act, g, lane, st);
-                res = lit.negate ? (act & ~X) : X;
+        // rows past the column's end (zero padding) are computed like any other and
+        // cleared when the tile is stored; the instrumented build masks them here
+        uint64_t act = ~0ull;
+        if (COUNT) act = valid_mask(w0 + k, c.n);
+        if (HAS_IN) act &= lane_word_c<k>(td.in);
+        const uint32_t b = (dw[k >> 2] >> (8 * (k & 3))) & 0xffu;
+        uint64_t res, plo, phi = 0;
+        if (MODE == kModeLT) {
+            res = ballot(b < clo) & act;
+            plo = ballot(b == clo) & act;
+        } else if (MODE == kModeGT) {
+            res = ballot(b > clo) & act;
+            plo = ballot(b == clo) & act;
+        } else if (MODE == kModeEQ) {
+            res = 0ull;
+            plo = ballot(b == clo) & act;
+        } else {
+            res = act & ~(ballot(b < clo) | ballot(b > chi));
+            plo = ballot(b == clo) & act;
+            phi = ballot(b == chi) & act;
+        }
+        if (COUNT) st.rowbytes += __builtin_popcountll(act);
+        if ((plo | phi) != 0) {
+            uint64_t hit = 0;
+            // the presence of byte 2 settles the rows equal on byte 1 that end here
+            const uint64_t m2 = DENSE ? has2 : lane_word_c<k>(td.m2);
+            if (COUNT && !DENSE && K >= 2) st.alg += 8;
+            level_mask_step<MODE>(plo, phi, hit, m2, k1lo, k1hi);
+            if (s2 && (plo | phi) != 0) {
+                // byte 2 from LDS (read in every lane; only pending lanes are used)
+                uint64_t P = plo | phi;
+                const uint32_t off2 =
+                    DENSE ? 64 * k + lane
+                          : sh2 + (k ? (uint32_t)__builtin_amdgcn_readlane((int)incl2, 2 * k - 1) : 0u) + mbcnt(m2);
+                if (COUNT) {
+                    st.alg += DENSE ? 64 : __builtin_popcountll(m2);
+                    st.rowbytes += __builtin_popcountll(P);
+                    st.deep_groups += 1;
+                }
+                byte_step<MODE>(plo, phi, hit, (uint32_t)lds2[off2], c2lo, c2hi);
+                if ((plo | phi) != 0) {
+                    const uint64_t m3 = DENSE ? has3 : lane_word_c<k>(m3v);
+                    if (COUNT && !DENSE && K >= 3) st.alg += 8;
+                    level_mask_step<MODE>(plo, phi, hit, m3, lit.k2lo, lit.k2hi);
+                    if (s3 && (plo | phi) != 0) {
+                        // byte 3 from LDS
+                        P = plo | phi;
+                        const uint32_t off3 =
+                            DENSE ? 64 * k + lane
+                                  : sh3 + (k ? (uint32_t)__builtin_amdgcn_readlane((int)incl3, 2 * k - 1) : 0u) +
+                                        mbcnt(m3);
+                        if (COUNT) {
+                            st.alg += DENSE ? 64 : __builtin_popcountll(m3);
+                            st.rowbytes += __builtin_popcountll(P);
+                        }
+                        byte_step<MODE>(plo, phi, hit, (uint32_t)lds3[off3], c3lo, c3hi);
+                        if ((plo | phi) != 0) {
+                            const uint64_t m4 = DENSE ? has4 : lane_word_c<k>(m4v);
+                            if (COUNT && !DENSE && K >= 4) st.alg += 8;
+                            level_mask_step<MODE>(plo, phi, hit, m4, lit.k3lo, lit.k3hi);
+                        }
+                    }
+                }
+            }
+            res = apply_hit<MODE>(res, hit);
+            if ((plo | phi) != 0) {
+                pend |= 1u << k;
+                plov = set_word_c<k>(plov, plo);
+                if (MODE == kModeBetween) phiv = set_word_c<k>(phiv, phi);
             }
         }
-        outv = put_lane<2 * k>(outv, (uint32_t)res);
-        outv = put_lane<2 * k + 1>(outv, (uint32_t)(res >> 32));
+        outv = set_word_c<k>(outv, res);
     });
+    // pass 2: bytes j0, j0+1, ... of the groups still pending
+    const uint32_t j0 = s3 ? 4u : (s2 ? 3u : 2u);
+    uint32_t cur_mv = 0;   // this lane's dword of the tile's M_j words (PP-VBS)
+    if (!DENSE && pend != 0) {
+        if (j0 == 2) cur_mv = td.m2;
+        else if (j0 == 3) cur_mv = m3v;
+        else cur_mv = m4v;
+    }
+    for (uint32_t j = j0; pend != 0 && j <= K; ++j) {
+        uint32_t next_mv = 0;   // M_{j+1}: which rows have a byte after this one
+        if (!DENSE && j < K) next_mv = reinterpret_cast<const uint32_t*>(c.m[j + 1])[t * 64 + lane];
+        uint32_t incl = 0;
+        uint64_t run0;
+        if (DENSE) {
+            run0 = t * kTileRows;
+        } else {
+            incl = wave_incl_sum(__builtin_popcount(cur_mv), lane);
+            run0 = c.dir[j][(t * kTileRows) >> c.dir_shift];
+        }
+        const uint32_t cjlo = lit_byte(lit.lo, j), cjhi = lit_byte(lit.hi, j);
+        uint32_t pend_next = 0;
+        {
+            while (pend) {
+                uint32_t ks[4];
+                uint32_t bb[4];
+                uint32_t cnt = 0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    ks[i] = 0;
+                    bb[i] = 0;
+                    if (pend) {
+                        const uint32_t k = __builtin_ctz(pend);
+                        pend &= pend - 1;
+                        ks[i] = k;
+                        cnt = i + 1;
+                        const uint64_t P = lane_word(plov, k) | (MODE == kModeBetween ? lane_word(phiv, k) : 0ull);
+                        const bool mine = (P >> lane) & 1;
+                        if (DENSE) {
+                            if (mine) bb[i] = c.bs[j][run0 + 64 * k + lane];
+                            if (COUNT) st.alg += 64;
+                        } else {
+                            const uint64_t mj = lane_word(cur_mv, k);
+                            const uint32_t before = k ? (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)(2 * k - 1)) : 0u;
+                            if (mine) bb[i] = c.bs[j][run0 + before + mbcnt(mj)];
+                            if (COUNT) st.alg += __builtin_popcountll(mj);
+                        }
+                        if (COUNT) {
+                            st.rowbytes += __builtin_popcountll(P);
+                            if (j == 2) st.deep_groups += 1;
+                        }
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if ((uint32_t)i < cnt) {
+                        const uint32_t k = ks[i];
+                        uint64_t plo = lane_word(plov, k);
+                        uint64_t phi = MODE == kModeBetween ? lane_word(phiv, k) : 0ull;
+                        uint64_t hit = 0;
+                        byte_step<MODE>(plo, phi, hit, bb[i], cjlo, cjhi);
+                        if ((plo | phi) != 0) {
+                            uint64_t m = 0;
+                            if (j < K) {
+                                if (DENSE) {
+                                    m = ~0ull;
+                                } else {
+                                    m = lane_word(next_mv, k);
+                                    if (COUNT) st.alg += 8;
+                                }
+                            }
+                            level_step<MODE>(plo, phi, hit, m, j, lit.llo, lit.lhi);
+                        }
+                        if (hit) outv = set_lane_word(outv, k, apply_hit<MODE>(lane_word(outv, k), hit), lane);
+                        if ((plo | phi) != 0) {
+                            pend_next |= 1u << k;
+                            plov = set_lane_word(plov, k, plo, lane);
+                            if (MODE == kModeBetween) phiv = set_lane_word(phiv, k, phi, lane);
+                        }
+                    }
+                }
+            }
+        }
+        pend = pend_next;
+        cur_mv = next_mv;
+    }
     const uint64_t d = w0 * 2 + lane;
-    if (d < nwords * 2) out32[d] = outv;
+    // the rows this lane's result dword may report: selected by the incoming mask and
+    // inside the column ('>=', '<=', '!=' complement within them)
+    uint32_t actv = td.in;
+    const bool full = (t + 1) * kTileRows <= c.n;
+    if (!full) {
+        const uint64_t r0 = d * 32;
+        actv &= r0 + 32 <= c.n ? ~0u : (r0 < c.n ? (1u << (c.n - r0)) - 1u : 0u);
+    }
+    if (MODE != kModeBetween && negate) outv = actv & ~outv;
+    else if (!full) outv &= actv;
+    if (full || d < nwords * 2) reinterpret_cast<uint32_t*>(out)[d] = outv;
+}
+
+// Load and scan one tile (used by the batched kernel).
+template <int MODE, bool DENSE, bool HAS_IN, bool COUNT>
+__device__ __forceinline__ void scan_slices_tile(const DevCol& c, const ScanLit& lit,
+                                                 const uint64_t* __restrict__ in_mask,
+                                                 uint64_t* __restrict__ out, uint64_t t, uint32_t lane,
+                                                 uint8_t* lds, Stats& st) {
+    const TileData td = load_tile<DENSE, HAS_IN>(c, in_mask, t, lane);
+    process_tile<MODE, -1, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, td, lds, st);
 }
 
 __device__ __forceinline__ void flush_stats(unsigned long long* counters, const Stats& st, uint32_t lane) {
@@ -342,8 +559,7 @@ __device__ __forceinline__ void scan_packed_tile(const DevCol& c, const PackedLi
         if (HAS_IN) act &= (g < nwords) ? in_mask[g] : 0ull;
         const uint64_t X = ballot(code - pl.a <= pl.span);
         const uint64_t res = pl.none ? 0ull : (pl.negate ? (act & ~X) : (act & X));
-        outv = put_lane<2 * k>(outv, (uint32_t)res);
-        outv = put_lane<2 * k + 1>(outv, (uint32_t)(res >> 32));
+        outv = put_word<k>(outv, (uint32_t)res, (uint32_t)(res >> 32));
     });
     const uint64_t d = w0 * 2 + lane;
     if (d < nwords * 2) out32[d] = outv;

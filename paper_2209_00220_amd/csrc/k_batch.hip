@@ -12,9 +12,9 @@ namespace dev {
 // Each layout / operator / width variant is its own out-of-line function, so
 // the dispatching kernel stays small and every variant is compiled on its own.
 template <int MODE, bool DENSE, bool HAS_IN>
-__device__ __noinline__ void batch_slices_tile(const BatchItem& it, uint64_t t, uint32_t lane) {
+__device__ __noinline__ void batch_slices_tile(const BatchItem& it, uint64_t t, uint32_t lane, uint8_t* lds) {
     Stats st;
-    scan_slices_tile<MODE, DENSE, HAS_IN, false>(it.c, it.lit, it.in_mask, it.out, t, lane, st);
+    scan_slices_tile<MODE, DENSE, HAS_IN, false>(it.c, it.lit, it.in_mask, it.out, t, lane, lds, st);
 }
 
 template <int W, bool HAS_IN>
@@ -23,7 +23,7 @@ __device__ __noinline__ void batch_packed_tile(const BatchItem& it, uint64_t t, 
     scan_packed_tile<W, HAS_IN>(it.c, it.pl, it.in_mask, it.out, t, lane, alg);
 }
 
-__device__ __forceinline__ void scan_any_tile(const BatchItem& it, uint64_t t, uint32_t lane) {
+__device__ __forceinline__ void scan_any_tile(const BatchItem& it, uint64_t t, uint32_t lane, uint8_t* lds) {
     const bool has_in = it.in_mask != nullptr;
     const uint32_t kind = it.kind;
     if (kind < 16) {
@@ -33,11 +33,11 @@ __device__ __forceinline__ void scan_any_tile(const BatchItem& it, uint64_t t, u
 #define BST_SLICE_CASE(MI, MODE)                                                 \
     if (mi == MI) {                                                              \
         if (dense) {                                                             \
-            if (has_in) batch_slices_tile<MODE, true, true>(it, t, lane);       \
-            else batch_slices_tile<MODE, true, false>(it, t, lane);             \
+            if (has_in) batch_slices_tile<MODE, true, true>(it, t, lane, lds);       \
+            else batch_slices_tile<MODE, true, false>(it, t, lane, lds);             \
         } else {                                                                 \
-            if (has_in) batch_slices_tile<MODE, false, true>(it, t, lane);      \
-            else batch_slices_tile<MODE, false, false>(it, t, lane);            \
+            if (has_in) batch_slices_tile<MODE, false, true>(it, t, lane, lds);      \
+            else batch_slices_tile<MODE, false, false>(it, t, lane, lds);            \
         }                                                                        \
         return;                                                                  \
     }
@@ -67,6 +67,8 @@ __device__ __forceinline__ void scan_any_tile(const BatchItem& it, uint64_t t, u
 __global__ __launch_bounds__(kBlock) void k_scan_batch(const BatchHeader* __restrict__ hdr,
                                                        const BatchItem* __restrict__ items,
                                                        unsigned long long* __restrict__ counter, uint32_t grab) {
+    __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerBlock][2 * kStageBytes];
+    uint8_t* lds = stage[threadIdx.x >> 6];
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t total = hdr->total_tiles;
     const uint32_t n_items = hdr->n_items;
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_batch(const BatchHeader* __rest
         for (uint64_t gt = start; gt < stop; ++gt) {
             while (cur + 1 < n_items && items[cur + 1].tile0 <= gt) ++cur;
             const BatchItem& it = items[cur];
-            scan_any_tile(it, gt - it.tile0, lane);
+            scan_any_tile(it, gt - it.tile0, lane, lds);
         }
     }
 }
@@ -153,6 +155,7 @@ int bst_batch_prepare(const bst_column* const* cols, const bst_pred* preds, cons
         memset(&it, 0, sizeof(it));
         it.c = col->dev;
         it.lit = lit;
+        choose_staging(*col->host, &it.lit, (int)g_tune[BST_TUNE_STAGE_PCT]);
         it.pl = packed_literal(*col->host, lit);
         it.in_mask = in;
         it.out = outs[i];

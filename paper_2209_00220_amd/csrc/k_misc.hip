@@ -158,7 +158,7 @@ DeviceProps& props() {
     return p;
 }
 
-int64_t g_tune[BST_TUNE_NKEYS] = {0, 0, 0, 4};
+int64_t g_tune[BST_TUNE_NKEYS] = {0, 0, 0, 4, 30};
 
 PackedLit packed_literal(const HostColumn& h, const ScanLit& s) {
     PackedLit p{0, 0, (uint32_t)s.negate, 0};
@@ -205,7 +205,9 @@ int run_scan(const bst_column* col, const ScanLit& lit, const uint64_t* in, uint
     if (c.n == 0) return BST_OK;
     if (lit.mode == kModeNone || lit.mode == kModeAll) return enqueue_fill(out, in, c.n, lit.mode == kModeAll ? 1 : 0, st);
     if (c.layout == BST_BITPACKED) return launch_packed(c, packed_literal(*col->host, lit), in, out, counters, st);
-    return launch_slices(c, lit, in, out, counters, st);
+    ScanLit staged = lit;
+    choose_staging(*col->host, &staged, (int)g_tune[BST_TUNE_STAGE_PCT]);
+    return launch_slices(c, staged, in, out, counters, st);
 }
 
 uint32_t batch_kind(const bst_column* col, const ScanLit& lit) {

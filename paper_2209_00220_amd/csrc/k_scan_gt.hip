@@ -1,0 +1,9 @@
+// Slice-layout scan kernels for literal mode kModeGT.
+#include "scan_kernel.h"
+
+namespace bst {
+namespace dev {
+template int launch_slices_mode<kModeGT>(const DevCol&, const ScanLit&, const uint64_t*, uint64_t*, unsigned long long*,
+                                    hipStream_t);
+}  // namespace dev
+}  // namespace bst
