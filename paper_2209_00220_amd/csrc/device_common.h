@@ -50,7 +50,7 @@ __device__ __forceinline__ uint32_t put_word(uint32_t v, uint32_t lo, uint32_t h
     uint32_t r;
     const uint32_t slo = __builtin_amdgcn_readfirstlane(lo);
     const uint32_t shi = __builtin_amdgcn_readfirstlane(hi);
-    asm volatile("s_nop 1\n\tv_writelane_b32 %0, %1, %3\n\tv_writelane_b32 %0, %2, %4"
+    asm("s_nop 1\n\tv_writelane_b32 %0, %1, %3\n\tv_writelane_b32 %0, %2, %4"
                  : "=v"(r)
                  : "s"(slo), "s"(shi), "i"(2 * K), "i"(2 * K + 1), "0"(v));
     return r;
@@ -321,7 +321,10 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
     const uint64_t k1hi = SHORT < 0 ? (1 < lit.lhi ? ~0ull : 0ull) : ((SHORT & 2) ? 0ull : ~0ull);
     // PP-VBS mask dwords are zero past the longest code; ByteSlice rows have all K bytes
     const uint64_t has2 = K >= 2 ? ~0ull : 0ull, has3 = K >= 3 ? ~0ull : 0ull, has4 = K >= 4 ? ~0ull : 0ull;
-    uint32_t outv = 0, plov = 0, phiv = 0, pend = 0;
+    // result words of groups k = 0, 1, 2, 3 (mod 4) build up in separate registers
+    // (disjoint lanes) so the lane writes of consecutive groups do not chain
+    uint32_t outq[4] = {0, 0, 0, 0};
+    uint32_t plov = 0, phiv = 0, pend = 0;
     Unroll<0, 32>::run([&](auto kc) {
         constexpr int k = decltype(kc)::value;
         // rows past the column's end (zero padding) are computed like any other and
@@ -395,8 +398,9 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
                 if (MODE == kModeBetween) phiv = set_word_c<k>(phiv, phi);
             }
         }
-        outv = set_word_c<k>(outv, res);
+        outq[k & 3] = set_word_c<k>(outq[k & 3], res);
     });
+    uint32_t outv = outq[0] | outq[1] | outq[2] | outq[3];
     // pass 2: bytes j0, j0+1, ... of the groups still pending
     const uint32_t j0 = s3 ? 4u : (s2 ? 3u : 2u);
     uint32_t cur_mv = 0;   // this lane's dword of the tile's M_j words (PP-VBS)
