@@ -267,6 +267,8 @@ def main():
         "p99_ms": None,
     }
     for lay in layouts:
+        progress("%-9s scan us per predicate: %s" % (lay, " ".join("%.0f" % (1e3 * v) for v in res[lay]["scan_ms"])))
+    for lay in layouts:
         progress("%-9s scan %.1f Gtuples/s  (%.0f GB/s algorithmic, %.1f%% of 8 TB/s)  lookup %s Mrows/s" % (
             lay, res[lay]["scan_gtuples"], res[lay]["alg_gbs"], 100 * res[lay]["alg_gbs"] / HBM_PEAK_GBS,
             "-" if res[lay]["lookup_mrows"] is None else "%.0f" % res[lay]["lookup_mrows"]))

@@ -303,8 +303,9 @@ enum {
     BST_TUNE_LOOKUP_GRID = 1,  /* workgroups of a lookup launch (0 = auto)             */
     BST_TUNE_BATCH_GRID = 2,   /* default workgroups of a batch launch (0 = auto)      */
     BST_TUNE_BATCH_GRAB = 3,   /* default tiles per grab of a batch launch             */
-    BST_TUNE_STAGE_PCT = 4,    /* stage a later slice per tile in LDS when at least this
-                                  percentage of 64-row groups is expected to need it   */
+    BST_TUNE_STAGE_PCT = 4,    /* a tile copies a later slice's run into LDS (one read)
+                                  instead of gathering group by group when at least
+                                  this percentage of its 64-row groups needs it       */
     BST_TUNE_NKEYS = 5
 };
 int bst_tune_set(int key, int64_t value);

@@ -40,20 +40,14 @@ __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Lanes 2K and 2K+1 of v take the uniform values lo and hi (v_writelane_b32 with
-// SGPR data).  The values usually come straight from a VALU compare or
-// readfirstlane, and a VALU read of an SGPR that a VALU instruction just wrote
-// needs two wait states on this chip; the compiler cannot see into the asm, so
-// the s_nop that provides them is part of it.
-template <int K>
-__device__ __forceinline__ uint32_t put_word(uint32_t v, uint32_t lo, uint32_t hi) {
-    uint32_t r;
-    const uint32_t slo = __builtin_amdgcn_readfirstlane(lo);
-    const uint32_t shi = __builtin_amdgcn_readfirstlane(hi);
-    asm("s_nop 1\n\tv_writelane_b32 %0, %1, %3\n\tv_writelane_b32 %0, %2, %4"
-                 : "=v"(r)
-                 : "s"(slo), "s"(shi), "i"(2 * K), "i"(2 * K + 1), "0"(v));
-    return r;
+// v_writelane: lane `lane` of `old` takes the uniform value `src` (the compiler
+// inserts the wait states that a preceding scalar write of `src` needs).
+__device__ int bst_writelane_i32(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+
+// Lanes 2k and 2k+1 of v take the low and high halves of the uniform word w.
+__device__ __forceinline__ uint32_t put_word_at(uint32_t v, uint32_t k, uint64_t w) {
+    v = (uint32_t)bst_writelane_i32((int)(uint32_t)w, (int)(2 * k), (int)v);
+    return (uint32_t)bst_writelane_i32((int)(uint32_t)(w >> 32), (int)(2 * k + 1), (int)v);
 }
 
 // Calls f(std::integral_constant<int, I>) for I = 0..N-1, unrolled at compile time.
@@ -125,19 +119,52 @@ struct TileData {
     uint32_t in;    // dword `lane` of the tile's 32 incoming-mask words (all ones when none)
 };
 
+// Raw buffer access (gfx9-family descriptor: no format, no swizzle).  A buffer
+// load past num_records returns zeros without touching memory, so every load
+// below is issued unconditionally: the hardware's in-order count of pending
+// loads then matches the program order exactly, and the compiler can wait for
+// one tile's data while the next tiles' loads stay in flight.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kRawBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRawBufferWord3);
+}
+
+__device__ __forceinline__ uint4 buffer_load16(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ uint32_t buffer_load4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+}
+
+// Lane's dword of the 32 mask words of tile t for level j (0 when the column has
+// no byte j, or when `valid` is false).
+__device__ __forceinline__ uint32_t load_mask_dword(const DevCol& c, uint32_t j, uint64_t t, uint32_t lane,
+                                                    bool valid = true) {
+    const bool has = valid && j <= c.K;
+    const void* base = has ? (const void*)(c.m[j] + t * 32) : (const void*)c.bs[1];
+    return buffer_load4(buffer_rsrc(base, has ? 256u : 0u), lane * 4);
+}
+
+// Loads of tile t (all zeros when `valid` is false: no memory is read).
 template <bool DENSE, bool HAS_IN>
 __device__ __forceinline__ TileData load_tile(const DevCol& c, const uint64_t* __restrict__ in_mask, uint64_t t,
-                                              uint32_t lane) {
+                                              uint32_t lane, bool valid = true) {
     TileData d;
-    const uint4* p = reinterpret_cast<const uint4*>(c.bs[1] + t * kTileRows) + lane * 2;
-    d.q0 = p[0];
-    d.q1 = p[1];
-    d.m2 = 0;
-    if (!DENSE && c.K >= 2) d.m2 = reinterpret_cast<const uint32_t*>(c.m[2])[t * 64 + lane];
+    const auto r1 = buffer_rsrc(c.bs[1] + (valid ? t * kTileRows : 0), valid ? kTileRows : 0u);
+    d.q0 = buffer_load16(r1, lane * 32);
+    d.q1 = buffer_load16(r1, lane * 32 + 16);
+    d.m2 = DENSE ? 0u : load_mask_dword(c, 2, t, lane, valid);
     d.in = ~0u;
     if (HAS_IN) {
-        const uint64_t dd = t * 64 + lane;
-        d.in = dd < ((c.n + 63) >> 6) * 2 ? reinterpret_cast<const uint32_t*>(in_mask)[dd] : 0u;
+        // the mask has ceil(n/64) words; the last tile may hold fewer than 32
+        const uint64_t nd = ((c.n + 63) >> 6) * 2, d0 = t * 64;
+        const uint32_t avail = (valid && d0 < nd) ? (uint32_t)(nd - d0 < 64 ? nd - d0 : 64) * 4u : 0u;
+        const void* base = avail ? (const void*)(reinterpret_cast<const uint32_t*>(in_mask) + d0) : (const void*)in_mask;
+        d.in = buffer_load4(buffer_rsrc(base, avail), lane * 4);
     }
     return d;
 }
@@ -146,13 +173,6 @@ __device__ __forceinline__ TileData load_tile(const DevCol& c, const uint64_t* _
 __device__ __forceinline__ uint64_t lane_word(uint32_t v, uint32_t k) {
     return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)v, (int)(2 * k)) |
            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)v, (int)(2 * k + 1)) << 32);
-}
-
-// Store the uniform 64-bit value w into lanes 2k and 2k+1 of v; k uniform.
-__device__ __forceinline__ uint32_t set_lane_word(uint32_t v, uint32_t k, uint64_t w, uint32_t lane) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)w);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(w >> 32));
-    return lane == 2 * k ? lo : (lane == 2 * k + 1 ? hi : v);
 }
 
 // Rows equal to the literal on bytes 1..j meet m (rows that have a byte j+1):
@@ -218,18 +238,6 @@ __device__ uint64_t full_read_bytes(const DevCol& c, const ScanLit& lit, uint64_
     return bytes;
 }
 
-// 64-bit word held by lanes 2K and 2K+1 of v, K a compile-time constant.
-template <int K>
-__device__ __forceinline__ uint64_t lane_word_c(uint32_t v) {
-    return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)v, 2 * K) |
-           ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)v, 2 * K + 1) << 32);
-}
-
-template <int K>
-__device__ __forceinline__ uint32_t set_word_c(uint32_t v, uint64_t w) {
-    return put_word<K>(v, (uint32_t)w, (uint32_t)(w >> 32));
-}
-
 // Inclusive prefix sum over the wave's lanes.
 __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v, uint32_t lane) {
 #pragma unroll
@@ -240,6 +248,23 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v, uint32_t lane) {
     return v;
 }
 
+// Sum over the wave's lanes (uniform).
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v, uint32_t lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_sum(v, lane), 63);
+}
+
+// Bit k set when the 64-bit word of group k (lanes 2k and 2k+1 of v) is non-zero.
+__device__ __forceinline__ uint32_t group_mask(uint32_t v) {
+    uint64_t b = ballot(v != 0);
+    b = (b | (b >> 1)) & 0x5555555555555555ull;   // group k's flag at bit 2k
+    b = (b | (b >> 1)) & 0x3333333333333333ull;   // then gather the even bits
+    b = (b | (b >> 2)) & 0x0f0f0f0f0f0f0f0full;
+    b = (b | (b >> 4)) & 0x00ff00ff00ff00ffull;
+    b = (b | (b >> 8)) & 0x0000ffff0000ffffull;
+    b = (b | (b >> 16)) & 0x00000000ffffffffull;
+    return (uint32_t)b;
+}
+
 constexpr uint32_t kStageBytes = 2080;   // 130 chunks of 16 bytes: a 2048-byte run plus alignment
 
 // Copy bytes [start, start+len) of a slice into this wave's LDS buffer with
@@ -247,238 +272,244 @@ constexpr uint32_t kStageBytes = 2080;   // 130 chunks of 16 bytes: a 2048-byte 
 __device__ __forceinline__ uint32_t stage_run(const uint8_t* __restrict__ src, uint64_t start, uint32_t len,
                                               uint8_t* buf, uint32_t lane) {
     const uint64_t a = start & ~15ull;
-    const uint64_t end = start + len;
-#pragma unroll
-    for (uint32_t i = lane; i < kStageBytes / 16; i += 64) {
-        const uint64_t p = a + 16ull * i;
-        if (p < end) *reinterpret_cast<uint4*>(buf + 16 * i) = *reinterpret_cast<const uint4*>(src + p);
-    }
+    // bytes from the aligned start, rounded up to whole 16-byte chunks: the range
+    // check drops a partly covered chunk, and slices carry 64 bytes of slack past
+    // their last byte, so the rounded range stays inside the allocation
+    const uint32_t span = (uint32_t)(start + len - a + 15) & ~15u;
+    const auto r = buffer_rsrc(src + a, span);
+    // 130 chunks: lanes 0..63 and 64..127 always, 128..129 by two lanes
+    const uint4 c0 = buffer_load16(r, 16 * lane);
+    const uint4 c1 = buffer_load16(r, 16 * (lane + 64));
+    uint4 c2 = make_uint4(0, 0, 0, 0);
+    if (lane < kStageBytes / 16 - 128) c2 = buffer_load16(r, 16 * (lane + 128));
+    *reinterpret_cast<uint4*>(buf + 16 * lane) = c0;
+    *reinterpret_cast<uint4*>(buf + 16 * (lane + 64)) = c1;
+    if (lane < kStageBytes / 16 - 128) *reinterpret_cast<uint4*>(buf + 16 * (lane + 128)) = c2;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     return (uint32_t)(start - a);
 }
 
-// One tile, one wave, in two passes.
+// One tile, one wave.
 //
-// Pass 1 walks the 32 groups (unrolled, first-slice bytes in registers) and
-// settles each group as deep as it can without waiting on memory: byte 1, the
-// presence of byte 2 (M_2, prefetched with the tile) and, when the launch
-// stages them, bytes 2 and 3 read from this wave's LDS copy of the tile's part
-// of BS_2 / BS_3 (one coalesced read each, made before the pass).  The host
-// stages a slice when many groups are expected to need it; otherwise pass 1
-// leaves those groups pending.
+// Byte 1: for each of the 32 groups (unrolled, the tile is in registers) the
+// ballots of the byte-1 compares land, as 64-bit words, in lanes 2k and 2k+1 of
+// three word vectors: `res` (rows decided in the relation; BETWEEN: rows in
+// range so far), `plo` / `phi` (rows equal so far to the lower / upper literal).
+// No branches, no scalar work per group.
 //
-// Pass 2 finishes the pending groups byte by byte: with many of them it stages
-// the slice in LDS, with few it gathers just their bytes, four groups in
-// flight.  Pending rows and results live in VGPR lanes (2k, 2k+1) per group.
+// Byte 2's presence: the tile's M_2 words sit in the same lane layout (one dword
+// per lane), so the length rules settle all 32 groups at once with a few
+// bitwise vector operations.
+//
+// Later bytes: only groups with rows still pending are visited, four at a time
+// (their reads issued before any is waited on).  Per level, a tile with many
+// pending groups copies its run of the slice into LDS with one coalesced read;
+// one with few gathers just the pending groups' bytes.  So later slices are read
+// only for undecided groups -- Algorithm 3's early stop at 64-row granularity,
+// tested wave-uniformly.
 template <int MODE, int SHORT, bool DENSE, bool HAS_IN, bool COUNT>
 __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit, uint64_t* __restrict__ out,
                                              uint64_t t, uint32_t lane, const TileData& td, uint8_t* lds,
                                              Stats& st) {
+    if (t >= c.ntiles) return;   // past the last tile (a prefetch slot with nothing to do)
     const uint64_t w0 = t * 32;
-    const uint64_t nwords = (c.n + 63) >> 6;
     const uint32_t K = c.K;
     const uint32_t clo = lit_byte(lit.lo, 1), chi = lit_byte(lit.hi, 1);
-    const uint32_t c2lo = lit_byte(lit.lo, 2), c2hi = lit_byte(lit.hi, 2);
-    const uint32_t c3lo = lit_byte(lit.lo, 3), c3hi = lit_byte(lit.hi, 3);
-    const bool negate = lit.negate != 0;
     const uint32_t dw[8] = {td.q0.x, td.q0.y, td.q0.z, td.q0.w, td.q1.x, td.q1.y, td.q1.z, td.q1.w};
+    // rows this lane's result dword may report: selected by the incoming mask and
+    // inside the column
+    const uint64_t d = w0 * 2 + lane;
+    const bool full = (t + 1) * kTileRows <= c.n;
+    uint32_t actv = HAS_IN ? td.in : ~0u;
+    if (!full) {
+        const uint64_t r0 = d * 32;
+        actv &= r0 + 32 <= c.n ? ~0u : (r0 < c.n ? (1u << (c.n - r0)) - 1u : 0u);
+    }
+    // SHORT bit 0 (bit 1): the lower (upper) literal is one byte long; SHORT < 0:
+    // the lengths are read at run time
+    constexpr bool kLoShort = SHORT >= 0 && (SHORT & 1) != 0;
+    constexpr bool kHiShort = SHORT >= 0 && (SHORT & 2) != 0;
+    // rows equal to a one-byte '<' or lower-BETWEEN literal on byte 1 are never
+    // below it: their equal-so-far ballot is not needed
+    constexpr bool kNeedLo = !((MODE == kModeLT || MODE == kModeBetween) && kLoShort);
+    const uint32_t klo = SHORT < 0 ? (1 < lit.llo ? ~0u : 0u) : (kLoShort ? 0u : ~0u);
+    const uint32_t khi = SHORT < 0 ? (1 < lit.lhi ? ~0u : 0u) : (kHiShort ? 0u : ~0u);
+    const uint32_t span1 = chi - clo;   // BETWEEN: byte 1 in [clo, chi]
+    // two registers per vector, alternating groups, so consecutive lane writes
+    // do not chain
+    uint32_t rq[2] = {0, 0}, pq[2] = {0, 0}, hq[2] = {0, 0};
+    Unroll<0, 32>::run([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const uint32_t b = (dw[k >> 2] >> (8 * (k & 3))) & 0xffu;
+        if (MODE == kModeLT) rq[k & 1] = put_word_at(rq[k & 1], k, ballot(b < clo));
+        if (MODE == kModeGT) rq[k & 1] = put_word_at(rq[k & 1], k, ballot(b > clo));
+        if (MODE == kModeBetween) rq[k & 1] = put_word_at(rq[k & 1], k, ballot(b - clo <= span1));
+        if (kNeedLo) pq[k & 1] = put_word_at(pq[k & 1], k, ballot(b == clo));
+        if (MODE == kModeBetween) hq[k & 1] = put_word_at(hq[k & 1], k, ballot(b == chi));
+    });
+    uint32_t outv = rq[0] | rq[1];
+    uint32_t plov = (pq[0] | pq[1]) & actv;
+    uint32_t phiv = (hq[0] | hq[1]) & actv;
     if (COUNT) {
         st.alg += kTileRows + 256 + (HAS_IN ? 256 : 0);
         st.full += full_read_bytes<DENSE>(c, lit, t, HAS_IN);
+        st.rowbytes += wave_sum(__builtin_popcount(actv), lane);
+        // M_2 words read: the groups with rows equal on byte 1
+        if (!DENSE && K >= 2) st.alg += 8ull * __builtin_popcount(group_mask(plov | phiv));
     }
-    // slices staged for pass 1
-    const bool s2 = (lit.stage & 1) && K >= 2;
-    const bool s3 = s2 && (lit.stage & 2) && K >= 3;
-    uint32_t m3v = 0, incl2 = 0, incl3 = 0, sh2 = 0, sh3 = 0;
-    uint8_t* lds2 = lds;
-    uint8_t* lds3 = lds + kStageBytes;
-    if (s2) {
-        if (!DENSE && K >= 3) m3v = reinterpret_cast<const uint32_t*>(c.m[3])[t * 64 + lane];
-        if (DENSE) {
-            sh2 = stage_run(c.bs[2], t * kTileRows, kTileRows, lds2, lane);
-        } else {
-            incl2 = wave_incl_sum(__builtin_popcount(td.m2), lane);
-            sh2 = stage_run(c.bs[2], c.dir[2][(t * kTileRows) >> c.dir_shift],
-                            (uint32_t)__builtin_amdgcn_readlane((int)incl2, 63), lds2, lane);
+    // byte 2's presence settles the rows equal on byte 1 that end there
+    {
+        const uint32_t m2v = DENSE ? (K >= 2 ? ~0u : 0u) : td.m2;
+        uint32_t hit;
+        if (MODE == kModeLT || MODE == kModeBetween) hit = plov & ~m2v & klo;   // a proper prefix: below
+        else if (MODE == kModeGT) hit = plov & m2v & ~klo;                     // equal, then more bytes: above
+        else hit = plov & ~m2v & ~klo;                                         // equal over the whole literal
+        plov &= m2v & klo;
+        if (MODE == kModeBetween) {
+            hit |= phiv & m2v & ~khi;
+            phiv &= m2v & khi;
         }
+        outv = MODE == kModeBetween ? (outv & ~hit) : (outv | hit);
     }
-    if (s3) {
-        if (DENSE) {
-            sh3 = stage_run(c.bs[3], t * kTileRows, kTileRows, lds3, lane);
-        } else {
-            incl3 = wave_incl_sum(__builtin_popcount(m3v), lane);
-            sh3 = stage_run(c.bs[3], c.dir[3][(t * kTileRows) >> c.dir_shift],
-                            (uint32_t)__builtin_amdgcn_readlane((int)incl3, 63), lds3, lane);
-        }
-    }
-    uint32_t m4v = 0;
-    if (s3 && !DENSE && K >= 4) m4v = reinterpret_cast<const uint32_t*>(c.m[4])[t * 64 + lane];
-    // byte 1: SHORT bit 0 (bit 1) says the lower (upper) literal is one byte long
-    // (SHORT < 0: decided at run time)
-    const uint64_t k1lo = SHORT < 0 ? (1 < lit.llo ? ~0ull : 0ull) : ((SHORT & 1) ? 0ull : ~0ull);
-    const uint64_t k1hi = SHORT < 0 ? (1 < lit.lhi ? ~0ull : 0ull) : ((SHORT & 2) ? 0ull : ~0ull);
-    // PP-VBS mask dwords are zero past the longest code; ByteSlice rows have all K bytes
-    const uint64_t has2 = K >= 2 ? ~0ull : 0ull, has3 = K >= 3 ? ~0ull : 0ull, has4 = K >= 4 ? ~0ull : 0ull;
-    // result words of groups k = 0, 1, 2, 3 (mod 4) build up in separate registers
-    // (disjoint lanes) so the lane writes of consecutive groups do not chain
-    uint32_t outq[4] = {0, 0, 0, 0};
-    uint32_t plov = 0, phiv = 0, pend = 0;
-    Unroll<0, 32>::run([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        // rows past the column's end (zero padding) are computed like any other and
-        // cleared when the tile is stored; the instrumented build masks them here
-        uint64_t act = ~0ull;
-        if (COUNT) act = valid_mask(w0 + k, c.n);
-        if (HAS_IN) act &= lane_word_c<k>(td.in);
-        const uint32_t b = (dw[k >> 2] >> (8 * (k & 3))) & 0xffu;
-        uint64_t res, plo, phi = 0;
-        if (MODE == kModeLT) {
-            res = ballot(b < clo) & act;
-            plo = ballot(b == clo) & act;
-        } else if (MODE == kModeGT) {
-            res = ballot(b > clo) & act;
-            plo = ballot(b == clo) & act;
-        } else if (MODE == kModeEQ) {
-            res = 0ull;
-            plo = ballot(b == clo) & act;
-        } else {
-            res = act & ~(ballot(b < clo) | ballot(b > chi));
-            plo = ballot(b == clo) & act;
-            phi = ballot(b == chi) & act;
-        }
-        if (COUNT) st.rowbytes += __builtin_popcountll(act);
-        if ((plo | phi) != 0) {
-            uint64_t hit = 0;
-            // the presence of byte 2 settles the rows equal on byte 1 that end here
-            const uint64_t m2 = DENSE ? has2 : lane_word_c<k>(td.m2);
-            if (COUNT && !DENSE && K >= 2) st.alg += 8;
-            level_mask_step<MODE>(plo, phi, hit, m2, k1lo, k1hi);
-            if (s2 && (plo | phi) != 0) {
-                // byte 2 from LDS (read in every lane; only pending lanes are used)
-                uint64_t P = plo | phi;
-                const uint32_t off2 =
-                    DENSE ? 64 * k + lane
-                          : sh2 + (k ? (uint32_t)__builtin_amdgcn_readlane((int)incl2, 2 * k - 1) : 0u) + mbcnt(m2);
-                if (COUNT) {
-                    st.alg += DENSE ? 64 : __builtin_popcountll(m2);
-                    st.rowbytes += __builtin_popcountll(P);
-                    st.deep_groups += 1;
-                }
-                byte_step<MODE>(plo, phi, hit, (uint32_t)lds2[off2], c2lo, c2hi);
-                if ((plo | phi) != 0) {
-                    const uint64_t m3 = DENSE ? has3 : lane_word_c<k>(m3v);
-                    if (COUNT && !DENSE && K >= 3) st.alg += 8;
-                    level_mask_step<MODE>(plo, phi, hit, m3, lit.k2lo, lit.k2hi);
-                    if (s3 && (plo | phi) != 0) {
-                        // byte 3 from LDS
-                        P = plo | phi;
-                        const uint32_t off3 =
-                            DENSE ? 64 * k + lane
-                                  : sh3 + (k ? (uint32_t)__builtin_amdgcn_readlane((int)incl3, 2 * k - 1) : 0u) +
-                                        mbcnt(m3);
-                        if (COUNT) {
-                            st.alg += DENSE ? 64 : __builtin_popcountll(m3);
-                            st.rowbytes += __builtin_popcountll(P);
-                        }
-                        byte_step<MODE>(plo, phi, hit, (uint32_t)lds3[off3], c3lo, c3hi);
-                        if ((plo | phi) != 0) {
-                            const uint64_t m4 = DENSE ? has4 : lane_word_c<k>(m4v);
-                            if (COUNT && !DENSE && K >= 4) st.alg += 8;
-                            level_mask_step<MODE>(plo, phi, hit, m4, lit.k3lo, lit.k3hi);
-                        }
-                    }
-                }
-            }
-            res = apply_hit<MODE>(res, hit);
-            if ((plo | phi) != 0) {
-                pend |= 1u << k;
-                plov = set_word_c<k>(plov, plo);
-                if (MODE == kModeBetween) phiv = set_word_c<k>(phiv, phi);
-            }
-        }
-        outq[k & 3] = set_word_c<k>(outq[k & 3], res);
-    });
-    uint32_t outv = outq[0] | outq[1] | outq[2] | outq[3];
-    // pass 2: bytes j0, j0+1, ... of the groups still pending
-    const uint32_t j0 = s3 ? 4u : (s2 ? 3u : 2u);
-    uint32_t cur_mv = 0;   // this lane's dword of the tile's M_j words (PP-VBS)
-    if (!DENSE && pend != 0) {
-        if (j0 == 2) cur_mv = td.m2;
-        else if (j0 == 3) cur_mv = m3v;
-        else cur_mv = m4v;
-    }
-    for (uint32_t j = j0; pend != 0 && j <= K; ++j) {
-        uint32_t next_mv = 0;   // M_{j+1}: which rows have a byte after this one
-        if (!DENSE && j < K) next_mv = reinterpret_cast<const uint32_t*>(c.m[j + 1])[t * 64 + lane];
+    // later bytes, pending groups only
+    // one-byte literals are settled by now (nothing stays pending); say so at
+    // compile time so the later-byte code drops out
+    constexpr bool kByte1Only = MODE == kModeBetween ? (kLoShort && kHiShort) : kLoShort;
+    uint32_t pend = kByte1Only ? 0u : group_mask(plov | phiv);
+    uint32_t cur_mv = DENSE ? 0u : td.m2;   // this lane's dword of the tile's M_j words
+    for (uint32_t j = 2; pend != 0 && j <= K; ++j) {
+        if (COUNT && j == 2) st.deep_groups += __builtin_popcount(pend);
+        const uint32_t next_mv = (!DENSE && j < K) ? load_mask_dword(c, j + 1, t, lane) : 0u;
         uint32_t incl = 0;
         uint64_t run0;
+        uint32_t runlen;
         if (DENSE) {
             run0 = t * kTileRows;
+            runlen = kTileRows;
         } else {
             incl = wave_incl_sum(__builtin_popcount(cur_mv), lane);
             run0 = c.dir[j][(t * kTileRows) >> c.dir_shift];
+            runlen = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
         }
+        // stage the tile's run of BS_j when enough groups need it
+        const bool staged = (uint32_t)__builtin_popcount(pend) >= lit.stage;
         const uint32_t cjlo = lit_byte(lit.lo, j), cjhi = lit_byte(lit.hi, j);
         uint32_t pend_next = 0;
-        {
-            while (pend) {
-                uint32_t ks[4];
-                uint32_t bb[4];
-                uint32_t cnt = 0;
+        if (staged) {
+            // the run is in LDS: walk the groups at compile-time positions, eight
+            // at a time, all eight LDS reads issued before the first compare
+            const uint32_t sh = stage_run(c.bs[j], run0, runlen, lds, lane);
+            if (COUNT) st.alg += DENSE ? 64ull * __builtin_popcount(pend) : 0ull;
+            Unroll<0, 4>::run([&](auto cc) {
+                constexpr int c8 = decltype(cc)::value * 8;
+                if ((pend >> c8) & 0xffu) {
+                    uint32_t bb[8];
+                    Unroll<0, 8>::run([&](auto ic) {
+                        constexpr int i = decltype(ic)::value, k = c8 + i;
+                        bb[i] = 0;
+                        if ((pend >> k) & 1u) {
+                            uint32_t pos;
+                            if (DENSE) {
+                                pos = 64 * k + lane;
+                            } else {
+                                const uint64_t mj = lane_word(cur_mv, k);
+                                pos = (k ? (uint32_t)__builtin_amdgcn_readlane((int)incl, 2 * k - 1) : 0u) + mbcnt(mj);
+                                if (COUNT) st.alg += __builtin_popcountll(mj);
+                            }
+                            bb[i] = lds[sh + pos];   // in bounds for every lane; pending lanes are used
+                        }
+                    });
+                    Unroll<0, 8>::run([&](auto ic) {
+                        constexpr int i = decltype(ic)::value, k = c8 + i;
+                        if ((pend >> k) & 1u) {
+                            uint64_t plo = lane_word(plov, k);
+                            uint64_t phi = MODE == kModeBetween ? lane_word(phiv, k) : 0ull;
+                            if (COUNT) st.rowbytes += __builtin_popcountll(plo | phi);
+                            uint64_t hit = 0;
+                            byte_step<MODE>(plo, phi, hit, bb[i], cjlo, cjhi);
+                            if ((plo | phi) != 0) {
+                                uint64_t m = 0;
+                                if (j < K) {
+                                    if (DENSE) {
+                                        m = ~0ull;
+                                    } else {
+                                        m = lane_word(next_mv, k);
+                                        if (COUNT) st.alg += 8;
+                                    }
+                                }
+                                level_step<MODE>(plo, phi, hit, m, j, lit.llo, lit.lhi);
+                            }
+                            if (hit) outv = put_word_at(outv, k, apply_hit<MODE>(lane_word(outv, k), hit));
+                            if ((plo | phi) != 0) {
+                                pend_next |= 1u << k;
+                                plov = put_word_at(plov, k, plo);
+                                if (MODE == kModeBetween) phiv = put_word_at(phiv, k, phi);
+                            }
+                        }
+                    });
+                }
+            });
+            pend = 0;
+        }
+        while (pend) {
+            uint32_t ks[4], bb[4];
+            uint32_t cnt = 0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    ks[i] = 0;
-                    bb[i] = 0;
-                    if (pend) {
-                        const uint32_t k = __builtin_ctz(pend);
-                        pend &= pend - 1;
-                        ks[i] = k;
-                        cnt = i + 1;
+            for (int i = 0; i < 4; ++i) {
+                ks[i] = 0;
+                bb[i] = 0;
+                if (pend) {
+                    const uint32_t k = __builtin_ctz(pend);
+                    pend &= pend - 1;
+                    ks[i] = k;
+                    cnt = i + 1;
+                    // row position of this lane's byte j within the tile's run
+                    uint32_t pos;
+                    if (DENSE) {
+                        pos = 64 * k + lane;
+                        if (COUNT) st.alg += 64;
+                    } else {
+                        const uint64_t mj = lane_word(cur_mv, k);
+                        const uint32_t before =
+                            k ? (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)(2 * k - 1)) : 0u;
+                        pos = before + mbcnt(mj);
+                        if (COUNT) st.alg += __builtin_popcountll(mj);
+                    }
+                    const uint64_t P = lane_word(plov, k) | (MODE == kModeBetween ? lane_word(phiv, k) : 0ull);
+                    if ((P >> lane) & 1) bb[i] = c.bs[j][run0 + pos];
+                    if (COUNT) {
                         const uint64_t P = lane_word(plov, k) | (MODE == kModeBetween ? lane_word(phiv, k) : 0ull);
-                        const bool mine = (P >> lane) & 1;
-                        if (DENSE) {
-                            if (mine) bb[i] = c.bs[j][run0 + 64 * k + lane];
-                            if (COUNT) st.alg += 64;
-                        } else {
-                            const uint64_t mj = lane_word(cur_mv, k);
-                            const uint32_t before = k ? (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)(2 * k - 1)) : 0u;
-                            if (mine) bb[i] = c.bs[j][run0 + before + mbcnt(mj)];
-                            if (COUNT) st.alg += __builtin_popcountll(mj);
-                        }
-                        if (COUNT) {
-                            st.rowbytes += __builtin_popcountll(P);
-                            if (j == 2) st.deep_groups += 1;
-                        }
+                        st.rowbytes += __builtin_popcountll(P);
                     }
                 }
+            }
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    if ((uint32_t)i < cnt) {
-                        const uint32_t k = ks[i];
-                        uint64_t plo = lane_word(plov, k);
-                        uint64_t phi = MODE == kModeBetween ? lane_word(phiv, k) : 0ull;
-                        uint64_t hit = 0;
-                        byte_step<MODE>(plo, phi, hit, bb[i], cjlo, cjhi);
-                        if ((plo | phi) != 0) {
-                            uint64_t m = 0;
-                            if (j < K) {
-                                if (DENSE) {
-                                    m = ~0ull;
-                                } else {
-                                    m = lane_word(next_mv, k);
-                                    if (COUNT) st.alg += 8;
-                                }
+            for (int i = 0; i < 4; ++i) {
+                if ((uint32_t)i < cnt) {
+                    const uint32_t k = ks[i];
+                    uint64_t plo = lane_word(plov, k);
+                    uint64_t phi = MODE == kModeBetween ? lane_word(phiv, k) : 0ull;
+                    uint64_t hit = 0;
+                    byte_step<MODE>(plo, phi, hit, bb[i], cjlo, cjhi);
+                    if ((plo | phi) != 0) {
+                        uint64_t m = 0;
+                        if (j < K) {
+                            if (DENSE) {
+                                m = ~0ull;
+                            } else {
+                                m = lane_word(next_mv, k);
+                                if (COUNT) st.alg += 8;
                             }
-                            level_step<MODE>(plo, phi, hit, m, j, lit.llo, lit.lhi);
                         }
-                        if (hit) outv = set_lane_word(outv, k, apply_hit<MODE>(lane_word(outv, k), hit), lane);
-                        if ((plo | phi) != 0) {
-                            pend_next |= 1u << k;
-                            plov = set_lane_word(plov, k, plo, lane);
-                            if (MODE == kModeBetween) phiv = set_lane_word(phiv, k, phi, lane);
-                        }
+                        level_step<MODE>(plo, phi, hit, m, j, lit.llo, lit.lhi);
+                    }
+                    if (hit) outv = put_word_at(outv, k, apply_hit<MODE>(lane_word(outv, k), hit));
+                    if ((plo | phi) != 0) {
+                        pend_next |= 1u << k;
+                        plov = put_word_at(plov, k, plo);
+                        if (MODE == kModeBetween) phiv = put_word_at(phiv, k, phi);
                     }
                 }
             }
@@ -486,18 +517,9 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
         pend = pend_next;
         cur_mv = next_mv;
     }
-    const uint64_t d = w0 * 2 + lane;
-    // the rows this lane's result dword may report: selected by the incoming mask and
-    // inside the column ('>=', '<=', '!=' complement within them)
-    uint32_t actv = td.in;
-    const bool full = (t + 1) * kTileRows <= c.n;
-    if (!full) {
-        const uint64_t r0 = d * 32;
-        actv &= r0 + 32 <= c.n ? ~0u : (r0 < c.n ? (1u << (c.n - r0)) - 1u : 0u);
-    }
-    if (MODE != kModeBetween && negate) outv = actv & ~outv;
-    else if (!full) outv &= actv;
-    if (full || d < nwords * 2) reinterpret_cast<uint32_t*>(out)[d] = outv;
+    if (MODE != kModeBetween && lit.negate) outv = actv & ~outv;
+    else outv &= actv;
+    if (full || d < ((c.n + 63) >> 6) * 2) reinterpret_cast<uint32_t*>(out)[d] = outv;
 }
 
 // Load and scan one tile (used by the batched kernel).
@@ -563,7 +585,7 @@ __device__ __forceinline__ void scan_packed_tile(const DevCol& c, const PackedLi
         if (HAS_IN) act &= (g < nwords) ? in_mask[g] : 0ull;
         const uint64_t X = ballot(code - pl.a <= pl.span);
         const uint64_t res = pl.none ? 0ull : (pl.negate ? (act & ~X) : (act & X));
-        outv = put_word<k>(outv, (uint32_t)res, (uint32_t)(res >> 32));
+        outv = put_word_at(outv, k, res);
     });
     const uint64_t d = w0 * 2 + lane;
     if (d < nwords * 2) out32[d] = outv;

@@ -346,43 +346,15 @@ static uint32_t bits_for(uint64_t nd) {
     return w;
 }
 
-// First-byte histograms from per-distinct codes and their row counts.
-static void build_hist(HostColumn& c, const uint64_t* counts) {
-    c.hist1.assign(256, 0);
-    c.hist2.assign(65536, 0);
-    for (uint64_t k = 0; k < c.nd; ++k) {
-        uint64_t code = c.code[k];
-        uint32_t len = c.clen[k];
-        if (c.layout == BST_BYTESLICE) code <<= (8 * c.K - c.width);
-        if (c.layout == BST_BITPACKED) continue;
-        const uint32_t b1 = (uint32_t)(code >> (8 * (len - 1))) & 0xff;
-        if (len >= 2) c.hist1[b1] += counts[k];
-        if (len >= 3) c.hist2[b1 * 256 + ((uint32_t)(code >> (8 * (len - 2))) & 0xff)] += counts[k];
-    }
-}
-
 void choose_staging(const HostColumn& c, ScanLit* s, int pct) {
+    (void)c;
     s->k2lo = 2 < s->llo ? ~0ull : 0ull;
     s->k2hi = 2 < s->lhi ? ~0ull : 0ull;
     s->k3lo = 3 < s->llo ? ~0ull : 0ull;
     s->k3hi = 3 < s->lhi ? ~0ull : 0ull;
-    s->stage = 0;
-    if (c.layout == BST_BITPACKED || c.n == 0 || c.hist1.empty() || pct <= 0 || pct > 100) return;
-    if (s->mode != kModeLT && s->mode != kModeGT && s->mode != kModeEQ && s->mode != kModeBetween) return;
-    auto b = [](uint64_t lit6, uint32_t j) { return (uint32_t)(lit6 >> (8 * (BST_KMAX - j))) & 0xff; };
-    const bool two = s->mode == kModeBetween;
-    double f2 = 0, f3 = 0;
-    if (s->llo >= 2) f2 += (double)c.hist1[b(s->lo, 1)];
-    if (two && s->lhi >= 2 && b(s->hi, 1) != b(s->lo, 1)) f2 += (double)c.hist1[b(s->hi, 1)];
-    if (s->llo >= 3) f3 += (double)c.hist2[b(s->lo, 1) * 256 + b(s->lo, 2)];
-    if (two && s->lhi >= 3 && (b(s->hi, 1) != b(s->lo, 1) || b(s->hi, 2) != b(s->lo, 2)))
-        f3 += (double)c.hist2[b(s->hi, 1) * 256 + b(s->hi, 2)];
-    const double n = (double)c.n;
-    // share of 64-row groups holding at least one row that needs the byte
-    const double g2 = 1.0 - std::pow(1.0 - std::min(1.0, f2 / n), 64.0);
-    const double g3 = 1.0 - std::pow(1.0 - std::min(1.0, f3 / n), 64.0);
-    if (g2 * 100.0 >= pct) s->stage |= 1;
-    if ((s->stage & 1) && g3 * 100.0 >= pct) s->stage |= 2;
+    // a tile stages a level's run when at least `stage` of its 32 groups need
+    // that level (33: never)
+    s->stage = (pct <= 0 || pct > 100) ? 33u : std::max<uint32_t>(1u, (uint32_t)((32 * pct + 99) / 100));
 }
 
 static int encode_column(const Dict& d, int layout, uint32_t width, uint32_t dir_stride, uint32_t T,
@@ -417,7 +389,6 @@ static int encode_column(const Dict& d, int layout, uint32_t width, uint32_t dir
         c.buf[BST_BUF_TRIE].resize(trie.size() * 4);
         if (!trie.empty()) memcpy(c.buf[BST_BUF_TRIE].data(), trie.data(), trie.size() * 4);
         build_vbs(c, d.rank.data(), T);
-        build_hist(c, d.Q.data());
         return BST_OK;
     }
     // fixed-length codes
@@ -448,7 +419,6 @@ static int encode_column(const Dict& d, int layout, uint32_t width, uint32_t dir
     if (layout == BST_BYTESLICE) {
         c.K = (c.width + 7) / 8;
         build_byteslice(c, vals, T);
-        build_hist(c, d.Q.data());
     } else {
         c.K = 1;
         build_bitpacked(c, vals, T);
@@ -699,7 +669,6 @@ int bst_encode_codes(const uint64_t* codes, const uint8_t* lengths, uint64_t n, 
     build_vbs(c, rank.data(), 1);
     std::vector<uint64_t> counts(c.nd, 0);
     for (uint64_t r = 0; r < n; ++r) counts[rank[r]]++;
-    build_hist(c, counts.data());
     *out = hc;
     return BST_OK;
 }

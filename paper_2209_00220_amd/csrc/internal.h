@@ -36,9 +36,6 @@ struct HostColumn {
     std::vector<uint8_t> buf[BST_NBUF];
     uint64_t rows_by_len[BST_KMAX + 1] = {0};
     uint32_t trie_root = kLeafFlag;
-    // rows whose code starts with byte b and has a second byte (hist1[b]), and rows
-    // whose code starts with bytes b1 b2 and has a third byte (hist2[b1 * 256 + b2])
-    std::vector<uint64_t> hist1, hist2;
 };
 
 // A literal in code space as the kernels take it.
@@ -47,7 +44,7 @@ struct ScanLit {
     int32_t negate;      // result = valid & ~X instead of X
     uint64_t lo, hi;     // slice layouts: codes padded to BST_KMAX bytes; Bit-Packed: plain codes
     uint32_t llo, lhi;   // code lengths in bytes (slice layouts)
-    uint32_t stage;      // bit 0: stage each tile's byte-2 slice in LDS; bit 1: also byte 3
+    uint32_t stage;      // pending groups (of 32) at which a tile stages a level's run in LDS
     uint32_t pad;
     // all ones while byte j is shorter than the literal (j < l), for j = 2, 3
     uint64_t k2lo, k2hi, k3lo, k3hi;
@@ -64,9 +61,9 @@ enum LitMode : int32_t {
 
 // Rewrite a value predicate into code space for a column (host, exact).
 int rewrite_predicate(const HostColumn& c, const bst_pred& p, ScanLit* out);
-// Decide which later slices a scan stages per tile (ScanLit.stage) from the
-// column's first-byte histograms: stage byte j when the expected share of 64-row
-// groups that need it reaches `pct` percent.
+// Set the scan's staging threshold (ScanLit.stage) from `pct`: a tile copies a
+// level's run of BS_j into LDS, instead of gathering bytes group by group, when
+// at least pct % of its 32 groups still have rows pending at that level.
 void choose_staging(const HostColumn& c, ScanLit* s, int pct);
 // Literal from explicit codes (op in code space).
 int code_literal(const HostColumn& c, int op, uint64_t lo, uint32_t llo, uint64_t hi, uint32_t lhi,

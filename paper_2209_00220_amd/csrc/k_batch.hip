@@ -67,7 +67,7 @@ __device__ __forceinline__ void scan_any_tile(const BatchItem& it, uint64_t t, u
 __global__ __launch_bounds__(kBlock) void k_scan_batch(const BatchHeader* __restrict__ hdr,
                                                        const BatchItem* __restrict__ items,
                                                        unsigned long long* __restrict__ counter, uint32_t grab) {
-    __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerBlock][2 * kStageBytes];
+    __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerBlock][kStageBytes];
     uint8_t* lds = stage[threadIdx.x >> 6];
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t total = hdr->total_tiles;
