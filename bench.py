@@ -97,6 +97,70 @@ def cpu_baseline(x, preds, sample_rows: int):
     }
 
 
+def serve_queries(x_counts, layouts, n_queries: int, seed: int):
+    """Queries over the benchmark column seen as a table whose columns are its
+    layouts: 1-3 predicates (selectivity log-uniform in [0.01 %, 50 %]) and a
+    lookup of one column."""
+    import numpy as np
+
+    from datagen import workloads
+    from paper_2209_00220_amd.serve import Query
+
+    v, c = x_counts
+    rng = np.random.default_rng(seed)
+    qs = []
+    for i in range(n_queries):
+        preds = []
+        for _ in range(int(rng.integers(1, 4))):
+            sel = float(np.exp(rng.uniform(np.log(1e-4), np.log(0.5))))
+            col = layouts[int(rng.integers(0, len(layouts)))]
+            kind = int(rng.integers(0, 3))
+            if kind == 0:
+                lo, _ = workloads.lit_lt(v, c, sel)
+                preds.append((col, "lt", lo, None))
+            elif kind == 1:
+                lo, _ = workloads.lit_lt(v, c, 1.0 - sel)
+                preds.append((col, "ge", lo, None))
+            else:
+                lo, hi, _ = workloads.lit_between(v, c, sel)
+                preds.append((col, "between", lo, hi))
+        qs.append(Query(i, "t", preds, [layouts[int(rng.integers(0, len(layouts)))]]))
+    return qs
+
+
+def serve_bench(dev_cols, x_counts, n_queries: int, budget_bytes: int):
+    """Saturation throughput of the continuous-batching server, then p50/p99 under
+    Poisson arrivals at half of it, served and one query at a time."""
+    from paper_2209_00220_amd.serve import GpuExecutor, Server, latency_summary, poisson_arrivals, run_serial
+
+    layouts = list(dev_cols)
+    ex = GpuExecutor({"t": dev_cols})
+    warm = serve_queries(x_counts, layouts, 8, seed=99)
+    Server(ex, budget_bytes).run(warm, keep_values=False)
+    qs = serve_queries(x_counts, layouts, n_queries, seed=5)
+    sat = latency_summary(Server(ex, budget_bytes).run(qs, keep_values=False))
+    sat_serial = latency_summary(run_serial(ex, qs, keep_values=False))
+    qps = 0.5 * sat["qps"]
+    arr = poisson_arrivals(n_queries, qps, seed=6)
+    for q, a in zip(qs, arr):
+        q.arrival = float(a)
+    srv = Server(ex, budget_bytes)
+    served = latency_summary(srv.run(qs, keep_values=False))
+    serial = latency_summary(run_serial(ex, qs, keep_values=False))
+    return {
+        "queries": n_queries,
+        "budget_bytes": budget_bytes,
+        "saturation_qps": round(sat["qps"], 1),
+        "saturation_qps_one_at_a_time": round(sat_serial["qps"], 1),
+        "offered_qps": round(qps, 1),
+        "p50_ms": round(served["p50_ms"], 3),
+        "p99_ms": round(served["p99_ms"], 3),
+        "one_at_a_time_p50_ms": round(serial["p50_ms"], 3),
+        "one_at_a_time_p99_ms": round(serial["p99_ms"], 3),
+        "mean_batch": round(sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)), 2),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +172,9 @@ def main():
     ap.add_argument("--layouts", default=",".join(LAYOUTS))
     ap.add_argument("--no-lookup", action="store_true")
     ap.add_argument("--preds", default="", help="comma-separated predicate indices to run (profiling)")
+    ap.add_argument("--serve-queries", type=int, default=200, help="queries of the serving run (0: skip)")
+    ap.add_argument("--no-batch", dest="batch", action="store_false", help="skip the batched-launch measurement")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (a plain copy kernel to scale memory counters)")
     args = ap.parse_args()
@@ -272,6 +339,30 @@ def main():
         progress("%-9s scan %.1f Gtuples/s  (%.0f GB/s algorithmic, %.1f%% of 8 TB/s)  lookup %s Mrows/s" % (
             lay, res[lay]["scan_gtuples"], res[lay]["alg_gbs"], 100 * res[lay]["alg_gbs"] / HBM_PEAK_GBS,
             "-" if res[lay]["lookup_mrows"] is None else "%.0f" % res[lay]["lookup_mrows"]))
+    if args.batch:
+        # the same step's scans as one persistent launch (replayed from a HIP graph)
+        from paper_2209_00220_amd.batch import Batch, autotune, time_call
+
+        progress("batched form: %d scans in one launch" % (len(layouts) * len(preds)))
+        specs = [(cols[lay][1], op, lo, hi, None) for lay in layouts for op, lo, hi, _ in preds]
+        outs = [cols[layouts[0]][1].new_bv() for _ in specs]
+        b = Batch(specs, outs)
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        best, table = autotune(b, grids=[cus * 4, cus * 8, cus * 16], grabs=(8, 16, 32, 64), repeats=3)
+        batch_ms = time_call(lambda: b.launch(best[0], best[1], True), repeats=5)
+        single_ms = float(sum(sum(res[lay]["scan_ms"]) for lay in layouts))
+        out["batch"] = {"scans": len(specs), "grid": best[0], "tiles_per_grab": best[1],
+                        "batch_ms": round(batch_ms, 3), "single_launches_ms": round(single_ms, 3),
+                        "batch_gtuples": round(n * len(specs) / (batch_ms * 1e-3) / 1e9, 1)}
+        progress("batch: %s" % json.dumps(out["batch"]))
+        b.close()
+        del outs
+    if args.serve_queries > 0:
+        progress("serving %d queries (continuous batching vs one at a time)" % args.serve_queries)
+        out["serving"] = serve_bench({lay: cols[lay][1] for lay in layouts}, workloads.value_counts(x, 20),
+                                     args.serve_queries, int(args.serve_budget_gb * (1 << 30)))
+        out["p99_ms"] = out["serving"]["p99_ms"]
+        progress("serving: %s" % json.dumps(out["serving"]))
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle) on %d rows" % args.cpu_sample)
         out["cpu_baseline"] = cpu_baseline(x, preds, min(args.cpu_sample, n))

@@ -312,8 +312,8 @@ __device__ __forceinline__ uint32_t stage_run(const uint8_t* __restrict__ src, u
 template <int MODE, int SHORT, bool DENSE, bool HAS_IN, bool COUNT>
 __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit, uint64_t* __restrict__ out,
                                              uint64_t t, uint32_t lane, const TileData& td, uint8_t* lds,
-                                             Stats& st) {
-    if (t >= c.ntiles) return;   // past the last tile (a prefetch slot with nothing to do)
+                                             Stats& st, uint64_t t_end) {
+    if (t >= t_end) return;   // past the wave's last tile (a prefetch slot with nothing to do)
     const uint64_t w0 = t * 32;
     const uint32_t K = c.K;
     const uint32_t clo = lit_byte(lit.lo, 1), chi = lit_byte(lit.hi, 1);
@@ -522,14 +522,34 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
     if (full || d < ((c.n + 63) >> 6) * 2) reinterpret_cast<uint32_t*>(out)[d] = outv;
 }
 
-// Load and scan one tile (used by the batched kernel).
-template <int MODE, bool DENSE, bool HAS_IN, bool COUNT>
-__device__ __forceinline__ void scan_slices_tile(const DevCol& c, const ScanLit& lit,
-                                                 const uint64_t* __restrict__ in_mask,
-                                                 uint64_t* __restrict__ out, uint64_t t, uint32_t lane,
-                                                 uint8_t* lds, Stats& st) {
-    const TileData td = load_tile<DENSE, HAS_IN>(c, in_mask, t, lane);
-    process_tile<MODE, -1, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, td, lds, st);
+// Scan tiles t_begin, t_begin + stride, ... below t_end, three tiles' loads in
+// flight: while one tile is scanned the next two are loading, and no register
+// is copied between tiles (a copy would wait for the load it copies).  The loop
+// has one exit, at the bottom, so every path through it issues the same loads
+// and each tile's wait leaves the next two in flight; a slot past the end loads
+// nothing and stores nothing.
+template <int MODE, int SHORT, bool DENSE, bool HAS_IN, bool COUNT>
+__device__ __forceinline__ void scan_slices_range(const DevCol& c, const ScanLit& lit,
+                                                  const uint64_t* __restrict__ in_mask,
+                                                  uint64_t* __restrict__ out, uint64_t t_begin, uint64_t t_end,
+                                                  uint64_t stride, uint32_t lane, uint8_t* lds, Stats& st) {
+    if (t_begin >= t_end) return;
+    uint64_t t = t_begin;
+    TileData a = load_tile<DENSE, HAS_IN>(c, in_mask, t, lane);
+    TileData b = load_tile<DENSE, HAS_IN>(c, in_mask, t + stride, lane, t + stride < t_end);
+    TileData d = load_tile<DENSE, HAS_IN>(c, in_mask, t + 2 * stride, lane, t + 2 * stride < t_end);
+    const uint64_t mine = (t_end - t_begin + stride - 1) / stride;
+    for (uint64_t i = 0; i < mine; i += 3) {
+        process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, a, lds, st, t_end);
+        a = load_tile<DENSE, HAS_IN>(c, in_mask, t + 3 * stride, lane, t + 3 * stride < t_end);
+        t += stride;
+        process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, b, lds, st, t_end);
+        b = load_tile<DENSE, HAS_IN>(c, in_mask, t + 3 * stride, lane, t + 3 * stride < t_end);
+        t += stride;
+        process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, d, lds, st, t_end);
+        d = load_tile<DENSE, HAS_IN>(c, in_mask, t + 3 * stride, lane, t + 3 * stride < t_end);
+        t += stride;
+    }
 }
 
 __device__ __forceinline__ void flush_stats(unsigned long long* counters, const Stats& st, uint32_t lane) {
@@ -663,6 +683,20 @@ struct BatchHeader {
     uint32_t n_items;
     uint32_t pad;
 };
+
+// Item holding group tile `g` of a batch group: the last item with tile0 <= g.
+__device__ __forceinline__ uint32_t batch_find(const BatchItem* __restrict__ items, uint32_t n_items, uint64_t g) {
+    uint32_t lo = 0, hi = n_items - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (items[mid].tile0 <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+using BatchKernel = void (*)(const BatchHeader*, const BatchItem*, unsigned long long*, uint32_t);
+// Persistent Bit-Packed batch kernel for code width w (nullptr outside 1..32).
+BatchKernel batch_packed_kernel(uint32_t w, bool has_in);
 
 
 // ------------------------------------------------------------ host helpers

@@ -9,100 +9,80 @@ using namespace bst::dev;
 namespace bst {
 namespace dev {
 
-// Each layout / operator / width variant is its own out-of-line function, so
-// the dispatching kernel stays small and every variant is compiled on its own.
+// Items of one group share a kernel variant (layout, operator or width, incoming
+// mask or not); tile0 counts tiles within the group.
+constexpr int kBatchGroupsMax = 2 * (4 * 2 + 32);   // (4 modes x 2 slice layouts + 32 widths) x in/out
+constexpr uint64_t kBatchHeaderBytes = 64;          // per group: BatchHeader, then the grab counter at +32
+
+// Waves take `grab` consecutive tiles of the group's concatenated tile list at a
+// time and scan them item by item (a grab may straddle items); the per-tile
+// work is the single-column scan's, inlined.
 template <int MODE, bool DENSE, bool HAS_IN>
-__device__ __noinline__ void batch_slices_tile(const BatchItem& it, uint64_t t, uint32_t lane, uint8_t* lds) {
-    Stats st;
-    scan_slices_tile<MODE, DENSE, HAS_IN, false>(it.c, it.lit, it.in_mask, it.out, t, lane, lds, st);
-}
-
-template <int W, bool HAS_IN>
-__device__ __noinline__ void batch_packed_tile(const BatchItem& it, uint64_t t, uint32_t lane) {
-    uint64_t alg = 0;
-    scan_packed_tile<W, HAS_IN>(it.c, it.pl, it.in_mask, it.out, t, lane, alg);
-}
-
-__device__ __forceinline__ void scan_any_tile(const BatchItem& it, uint64_t t, uint32_t lane, uint8_t* lds) {
-    const bool has_in = it.in_mask != nullptr;
-    const uint32_t kind = it.kind;
-    if (kind < 16) {
-        // slice layouts: bit 0 dense (ByteSlice), bits 1..2 literal mode
-        const bool dense = kind & 1;
-        const int mi = (kind >> 1) & 3;
-#define BST_SLICE_CASE(MI, MODE)                                                 \
-    if (mi == MI) {                                                              \
-        if (dense) {                                                             \
-            if (has_in) batch_slices_tile<MODE, true, true>(it, t, lane, lds);       \
-            else batch_slices_tile<MODE, true, false>(it, t, lane, lds);             \
-        } else {                                                                 \
-            if (has_in) batch_slices_tile<MODE, false, true>(it, t, lane, lds);      \
-            else batch_slices_tile<MODE, false, false>(it, t, lane, lds);            \
-        }                                                                        \
-        return;                                                                  \
-    }
-        BST_SLICE_CASE(0, kModeLT)
-        BST_SLICE_CASE(1, kModeGT)
-        BST_SLICE_CASE(2, kModeEQ)
-        BST_SLICE_CASE(3, kModeBetween)
-#undef BST_SLICE_CASE
-        return;
-    }
-    switch (kind - 16) {
-#define BST_W(W)                                               \
-    case W:                                                    \
-        if (has_in) batch_packed_tile<W, true>(it, t, lane);  \
-        else batch_packed_tile<W, false>(it, t, lane);        \
-        return;
-        BST_W(1) BST_W(2) BST_W(3) BST_W(4) BST_W(5) BST_W(6) BST_W(7) BST_W(8)
-        BST_W(9) BST_W(10) BST_W(11) BST_W(12) BST_W(13) BST_W(14) BST_W(15) BST_W(16)
-        BST_W(17) BST_W(18) BST_W(19) BST_W(20) BST_W(21) BST_W(22) BST_W(23) BST_W(24)
-        BST_W(25) BST_W(26) BST_W(27) BST_W(28) BST_W(29) BST_W(30) BST_W(31) BST_W(32)
-#undef BST_W
-        default:
-            return;
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_scan_batch(const BatchHeader* __restrict__ hdr,
-                                                       const BatchItem* __restrict__ items,
-                                                       unsigned long long* __restrict__ counter, uint32_t grab) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMinWaves, 8))) void k_batch_slices(
+    const BatchHeader* __restrict__ hdr, const BatchItem* __restrict__ items, unsigned long long* __restrict__ counter,
+    uint32_t grab) {
     __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerBlock][kStageBytes];
     uint8_t* lds = stage[threadIdx.x >> 6];
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t total = hdr->total_tiles;
     const uint32_t n_items = hdr->n_items;
+    Stats st;
     for (;;) {
         uint64_t start = 0;
         if (lane == 0) start = atomicAdd(counter, (unsigned long long)grab);
         start = ((uint64_t)uniform((uint32_t)(start >> 32)) << 32) | uniform((uint32_t)start);
         if (start >= total) break;
         const uint64_t stop = std::min<uint64_t>(total, start + grab);
-        // item holding `start`: last item with tile0 <= start
-        uint32_t lo = 0, hi = n_items - 1;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi + 1) >> 1;
-            if (items[mid].tile0 <= start) lo = mid; else hi = mid - 1;
-        }
-        uint32_t cur = lo;
-        for (uint64_t gt = start; gt < stop; ++gt) {
-            while (cur + 1 < n_items && items[cur + 1].tile0 <= gt) ++cur;
+        for (uint32_t cur = batch_find(items, n_items, start); cur < n_items && items[cur].tile0 < stop; ++cur) {
             const BatchItem& it = items[cur];
-            scan_any_tile(it, gt - it.tile0, lane, lds);
+            const uint64_t b0 = std::max<uint64_t>(start, it.tile0) - it.tile0;
+            const uint64_t b1 = std::min<uint64_t>(stop, it.tile0 + it.c.ntiles) - it.tile0;
+            scan_slices_range<MODE, -1, DENSE, HAS_IN, false>(it.c, it.lit, it.in_mask, it.out, b0, b1, 1, lane, lds,
+                                                               st);
         }
     }
 }
 
-__global__ void k_reset_counter(unsigned long long* counter) {
-    if (threadIdx.x == 0) *counter = 0;
+// Zero the groups' grab counters (a fill kernel, so the launch sequence can be
+// captured in a graph).
+__global__ void k_reset_counters(char* __restrict__ ws, int n_groups) {
+    const int g = threadIdx.x;
+    if (g < n_groups) *reinterpret_cast<unsigned long long*>(ws + g * kBatchHeaderBytes + 32) = 0;
+}
+
+
+// Kernel of a group: kind (see batch_kind) and whether its items have an incoming mask.
+static BatchKernel batch_kernel(uint32_t kind, bool has_in) {
+    if (kind < 16) {
+        const bool dense = kind & 1;
+        const int mi = (kind >> 1) & 3;
+#define BST_K(MODE)                                                                              \
+    return dense ? (has_in ? k_batch_slices<MODE, true, true> : k_batch_slices<MODE, true, false>) \
+                 : (has_in ? k_batch_slices<MODE, false, true> : k_batch_slices<MODE, false, false>)
+        switch (mi) {
+            case 0: BST_K(kModeLT);
+            case 1: BST_K(kModeGT);
+            case 2: BST_K(kModeEQ);
+            default: BST_K(kModeBetween);
+        }
+#undef BST_K
+    }
+    return batch_packed_kernel(kind - 16, has_in);
 }
 
 }  // namespace dev
 }  // namespace bst
 
+struct BatchGroup {
+    uint32_t kind;
+    bool has_in;
+    uint32_t first, count;   // items [first, first + count) of the sorted item list
+    uint64_t tiles;
+};
+
 struct bst_batch {
-    std::vector<BatchItem> items;
-    BatchHeader hdr;
+    std::vector<BatchItem> items;        // sorted by group
+    std::vector<BatchGroup> groups;
     std::vector<std::pair<uint64_t*, std::pair<const uint64_t*, int>>> fills;   // (out, (in, all)) for ALL/NONE items
     std::vector<uint64_t> fill_rows;
     void* ws = nullptr;
@@ -118,7 +98,7 @@ extern "C" {
 // ---- batch ---------------------------------------------------------------
 uint64_t bst_batch_workspace_bytes(int n_items) {
     if (n_items < 0) return 0;
-    return 256 + (uint64_t)n_items * sizeof(BatchItem) + 256;
+    return (uint64_t)kBatchGroupsMax * kBatchHeaderBytes + (uint64_t)n_items * sizeof(BatchItem);
 }
 
 int bst_batch_prepare(const bst_column* const* cols, const bst_pred* preds, const uint64_t* const* in_masks,
@@ -164,25 +144,49 @@ int bst_batch_prepare(const bst_column* const* cols, const bst_pred* preds, cons
         tiles += col->dev.ntiles;
         b->items.push_back(it);
     }
-    b->hdr.total_tiles = tiles;
-    b->hdr.n_items = (uint32_t)b->items.size();
+    // group the items by kernel variant, keeping their order within a group
+    std::vector<BatchItem> sorted;
+    sorted.reserve(b->items.size());
+    std::vector<bool> used(b->items.size(), false);
+    for (size_t i = 0; i < b->items.size(); ++i) {
+        if (used[i]) continue;
+        BatchGroup g{b->items[i].kind, b->items[i].in_mask != nullptr, (uint32_t)sorted.size(), 0, 0};
+        for (size_t j = i; j < b->items.size(); ++j) {
+            if (used[j] || b->items[j].kind != g.kind || (b->items[j].in_mask != nullptr) != g.has_in) continue;
+            used[j] = true;
+            BatchItem it = b->items[j];
+            it.tile0 = g.tiles;
+            g.tiles += it.c.ntiles;
+            sorted.push_back(it);
+            ++g.count;
+        }
+        if (!batch_kernel(g.kind, g.has_in)) {
+            delete b;
+            return set_error(BST_EINVAL, "no batch kernel for this column");
+        }
+        b->groups.push_back(g);
+    }
+    b->items.swap(sorted);
+    (void)tiles;
     *out = b;
     return BST_OK;
 }
 
 static int batch_enqueue(bst_batch* b, uint32_t grid, uint32_t grab, hipStream_t st) {
     char* ws = (char*)b->ws;
-    BatchHeader* hdr = (BatchHeader*)ws;
-    unsigned long long* counter = (unsigned long long*)(ws + 128);
-    BatchItem* items = (BatchItem*)(ws + 256);
+    const BatchItem* items = (const BatchItem*)(ws + (uint64_t)kBatchGroupsMax * kBatchHeaderBytes);
     for (size_t i = 0; i < b->fills.size(); ++i) {
         int rc = enqueue_fill(b->fills[i].first, b->fills[i].second.first, b->fill_rows[i], b->fills[i].second.second, st);
         if (rc) return rc;
     }
-    if (!b->items.empty()) {
-        hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, st, counter);
-        hipLaunchKernelGGL(k_scan_batch, dim3(grid), dim3(kBlock), 0, st, (const BatchHeader*)hdr,
-                           (const BatchItem*)items, counter, grab);
+    if (!b->groups.empty()) {
+        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(128), 0, st, ws, (int)b->groups.size());
+        for (size_t g = 0; g < b->groups.size(); ++g) {
+            const BatchGroup& gr = b->groups[g];
+            char* h = ws + g * kBatchHeaderBytes;
+            hipLaunchKernelGGL(batch_kernel(gr.kind, gr.has_in), dim3(grid), dim3(kBlock), 0, st,
+                               (const BatchHeader*)h, items + gr.first, (unsigned long long*)(h + 32), grab);
+        }
     }
     return hip_check(hipGetLastError(), "batch launch");
 }
@@ -191,12 +195,17 @@ int bst_batch_launch(bst_batch* b, uint32_t grid, uint32_t tiles_per_grab, int u
     if (!b) return set_error(BST_EINVAL, "NULL batch");
     hipStream_t st = (hipStream_t)stream;
     if (grid == 0) grid = g_tune[BST_TUNE_BATCH_GRID] > 0 ? (uint32_t)g_tune[BST_TUNE_BATCH_GRID] : (uint32_t)props().cus * 8;
-    if (tiles_per_grab == 0) tiles_per_grab = g_tune[BST_TUNE_BATCH_GRAB] > 0 ? (uint32_t)g_tune[BST_TUNE_BATCH_GRAB] : 4;
+    if (tiles_per_grab == 0) tiles_per_grab = g_tune[BST_TUNE_BATCH_GRAB] > 0 ? (uint32_t)g_tune[BST_TUNE_BATCH_GRAB] : 16;
     if (!b->uploaded) {
         char* ws = (char*)b->ws;
-        int rc = hip_check(hipMemcpyAsync(ws, &b->hdr, sizeof(b->hdr), hipMemcpyHostToDevice, st), "batch upload");
+        std::vector<char> head((size_t)kBatchGroupsMax * kBatchHeaderBytes, 0);
+        for (size_t g = 0; g < b->groups.size(); ++g) {
+            BatchHeader h{b->groups[g].tiles, b->groups[g].count, 0};
+            memcpy(head.data() + g * kBatchHeaderBytes, &h, sizeof(h));
+        }
+        int rc = hip_check(hipMemcpyAsync(ws, head.data(), head.size(), hipMemcpyHostToDevice, st), "batch upload");
         if (!rc && !b->items.empty())
-            rc = hip_check(hipMemcpyAsync(ws + 256, b->items.data(), b->items.size() * sizeof(BatchItem),
+            rc = hip_check(hipMemcpyAsync(ws + head.size(), b->items.data(), b->items.size() * sizeof(BatchItem),
                                           hipMemcpyHostToDevice, st), "batch upload");
         if (!rc) rc = hip_check(hipStreamSynchronize(st), "batch upload sync");
         if (rc) return rc;

@@ -1,0 +1,46 @@
+// Batched Bit-Packed scans: one persistent kernel per code width (own
+// translation unit, compiled alongside the slice-layout batch kernels).
+#include "device_common.h"
+
+namespace bst {
+namespace dev {
+
+template <int W, bool HAS_IN>
+__global__ __launch_bounds__(kBlock) void k_batch_packed(const BatchHeader* __restrict__ hdr,
+                                                         const BatchItem* __restrict__ items,
+                                                         unsigned long long* __restrict__ counter, uint32_t grab) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t total = hdr->total_tiles;
+    const uint32_t n_items = hdr->n_items;
+    uint64_t alg = 0;
+    for (;;) {
+        uint64_t start = 0;
+        if (lane == 0) start = atomicAdd(counter, (unsigned long long)grab);
+        start = ((uint64_t)uniform((uint32_t)(start >> 32)) << 32) | uniform((uint32_t)start);
+        if (start >= total) break;
+        const uint64_t stop = std::min<uint64_t>(total, start + grab);
+        for (uint32_t cur = batch_find(items, n_items, start); cur < n_items && items[cur].tile0 < stop; ++cur) {
+            const BatchItem& it = items[cur];
+            const uint64_t b0 = std::max<uint64_t>(start, it.tile0) - it.tile0;
+            const uint64_t b1 = std::min<uint64_t>(stop, it.tile0 + it.c.ntiles) - it.tile0;
+#pragma nounroll
+            for (uint64_t t = b0; t < b1; ++t) scan_packed_tile<W, HAS_IN>(it.c, it.pl, it.in_mask, it.out, t, lane, alg);
+        }
+    }
+}
+
+BatchKernel batch_packed_kernel(uint32_t w, bool has_in) {
+    switch (w) {
+#define BST_W(W) \
+    case W: return has_in ? k_batch_packed<W, true> : k_batch_packed<W, false>;
+        BST_W(1) BST_W(2) BST_W(3) BST_W(4) BST_W(5) BST_W(6) BST_W(7) BST_W(8)
+        BST_W(9) BST_W(10) BST_W(11) BST_W(12) BST_W(13) BST_W(14) BST_W(15) BST_W(16)
+        BST_W(17) BST_W(18) BST_W(19) BST_W(20) BST_W(21) BST_W(22) BST_W(23) BST_W(24)
+        BST_W(25) BST_W(26) BST_W(27) BST_W(28) BST_W(29) BST_W(30) BST_W(31) BST_W(32)
+#undef BST_W
+        default: return nullptr;
+    }
+}
+
+}  // namespace dev
+}  // namespace bst

@@ -158,7 +158,7 @@ DeviceProps& props() {
     return p;
 }
 
-int64_t g_tune[BST_TUNE_NKEYS] = {0, 0, 0, 4, 30};
+int64_t g_tune[BST_TUNE_NKEYS] = {0, 0, 0, 16, 30};
 
 PackedLit packed_literal(const HostColumn& h, const ScanLit& s) {
     PackedLit p{0, 0, (uint32_t)s.negate, 0};

@@ -17,31 +17,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMinWave
     const uint32_t wave = uniform(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
     Stats st;
-    uint64_t t = wave;
-    const uint64_t nt = c.ntiles;
-    if (t < nt) {
-        // three tiles' registers in rotation: while one tile is scanned the loads
-        // of the next two are in flight, and no register is copied between tiles
-        // (a copy would wait for the load it copies)
-        // a tile index past the end loads nothing and its processing stores nothing;
-        // the loop has one exit, at the bottom, so every path through it issues the
-        // same loads and each tile's wait leaves the next two tiles in flight
-        TileData a = load_tile<DENSE, HAS_IN>(c, in_mask, t, lane);
-        TileData b = load_tile<DENSE, HAS_IN>(c, in_mask, t + nwaves, lane, t + nwaves < nt);
-        TileData d = load_tile<DENSE, HAS_IN>(c, in_mask, t + 2ull * nwaves, lane, t + 2ull * nwaves < nt);
-        const uint64_t mine = (nt - t + nwaves - 1) / nwaves;   // tiles of this wave
-        for (uint64_t i = 0; i < mine; i += 3) {
-            process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, a, lds, st);
-            a = load_tile<DENSE, HAS_IN>(c, in_mask, t + 3ull * nwaves, lane, t + 3ull * nwaves < nt);
-            t += nwaves;
-            process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, b, lds, st);
-            b = load_tile<DENSE, HAS_IN>(c, in_mask, t + 3ull * nwaves, lane, t + 3ull * nwaves < nt);
-            t += nwaves;
-            process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, d, lds, st);
-            d = load_tile<DENSE, HAS_IN>(c, in_mask, t + 3ull * nwaves, lane, t + 3ull * nwaves < nt);
-            t += nwaves;
-        }
-    }
+    scan_slices_range<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, in_mask, out, wave, c.ntiles, nwaves, lane, lds, st);
     if (COUNT) flush_stats(counters, st, lane);
 }
 

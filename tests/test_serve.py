@@ -1,0 +1,181 @@
+"""Serving loop (admission by output bytes, continuous batching) driven on the
+host: every query's result equals the plain scan-and-lookup of Sec. 2.2 on the
+raw values, alone or in a mix, and the scheduler keeps its memory budget."""
+import numpy as np
+import pytest
+
+from oracle.scan import scan_values
+from paper_2209_00220_amd.serve import Query, Server, latency_summary, poisson_arrivals, run_serial
+
+
+class HostExecutor:
+    """Executes the server's steps with plain numpy on raw value columns."""
+
+    def __init__(self, tables, step_cost=0.0, clock=None):
+        self.tables = tables
+        self.steps = []
+        self.step_cost = step_cost
+        self.clock = clock
+
+    def n_rows(self, t):
+        return next(iter(self.tables[t].values())).shape[0]
+
+    def bv_bytes(self, t):
+        return 8 * ((self.n_rows(t) + 63) // 64)
+
+    def new_bv(self, t):
+        return np.zeros(self.n_rows(t), dtype=bool)
+
+    def scan_step(self, items):
+        self.steps.append([(t, c, op, lo, hi, inb is not None) for t, c, op, lo, hi, inb, _ in items])
+        for t, c, op, lo, hi, inb, out in items:
+            out[:] = scan_values(self.tables[t][c], op, lo, hi, in_mask=inb)
+        if self.clock is not None:
+            self.clock.t += self.step_cost
+
+    def count(self, t, bv):
+        return int(bv.sum())
+
+    def lookup(self, t, c, bv, count):
+        return self.tables[t][c][bv].copy()
+
+    def finish(self, values):
+        pass
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += dt
+
+
+def _tables(seed=0):
+    rng = np.random.default_rng(seed)
+    return {
+        "a": {c: rng.integers(0, 1 << 12, 5000, dtype=np.uint32) for c in ("c0", "c1", "c2")},
+        "b": {c: rng.integers(0, 1 << 20, 3001, dtype=np.uint32) for c in ("d0", "d1")},
+    }
+
+
+def _queries(tables, n, seed, arrivals=None):
+    rng = np.random.default_rng(seed)
+    ops = ["lt", "le", "gt", "ge", "eq", "ne", "between"]
+    qs = []
+    for i in range(n):
+        t = ["a", "b"][int(rng.integers(0, 2))]
+        cols = list(tables[t])
+        preds = []
+        for _ in range(int(rng.integers(1, 5))):
+            c = cols[int(rng.integers(0, len(cols)))]
+            x = tables[t][c]
+            lo, hi = sorted(int(v) for v in x[rng.integers(0, x.shape[0], 2)])
+            op = ops[int(rng.integers(0, len(ops)))]
+            preds.append((c, op, lo, hi if op == "between" else None))
+        look = [cols[int(j)] for j in rng.choice(len(cols), size=int(rng.integers(1, 3)), replace=False)]
+        qs.append(Query(i, t, preds, look, 0.0 if arrivals is None else float(arrivals[i])))
+    return qs
+
+
+def _plain(tables, q):
+    sel = None
+    for c, op, lo, hi in q.preds:
+        sel = scan_values(tables[q.table][c], op, lo, hi, in_mask=sel)
+    return {c: tables[q.table][c][sel] for c in q.lookups}, int(sel.sum())
+
+
+def test_results_equal_plain_scan_and_lookup():
+    tables = _tables()
+    qs = _queries(tables, 40, seed=1)
+    res = Server(HostExecutor(tables), budget_bytes=1 << 30).run(qs)
+    for q in qs:
+        want, cnt = _plain(tables, q)
+        assert res[q.qid].count == cnt
+        for c in q.lookups:
+            assert np.array_equal(res[q.qid].values[c], want[c])
+
+
+def test_alone_equals_in_mix():
+    tables = _tables(3)
+    qs = _queries(tables, 30, seed=4)
+    mix = Server(HostExecutor(tables), budget_bytes=1 << 30).run(qs)
+    for q in qs:
+        alone = Server(HostExecutor(tables), budget_bytes=1 << 30).run([q])[q.qid]
+        assert alone.count == mix[q.qid].count
+        for c in q.lookups:
+            assert np.array_equal(alone.values[c], mix[q.qid].values[c])
+    serial = run_serial(HostExecutor(tables), qs)
+    for q in qs:
+        assert serial[q.qid].count == mix[q.qid].count
+
+
+def test_continuous_batching_one_predicate_per_step():
+    tables = _tables()
+    qs = _queries(tables, 10, seed=2)
+    ex = HostExecutor(tables)
+    Server(ex, budget_bytes=1 << 30).run(qs)
+    # all arrive at 0: step s carries the s-th predicate of every query with more than s
+    for s, step in enumerate(ex.steps):
+        assert len(step) == sum(1 for q in qs if len(q.preds) > s)
+        assert all(has_in == (s > 0) for *_, has_in in step)
+    assert len(ex.steps) == max(len(q.preds) for q in qs)
+
+
+def test_budget_limits_admission():
+    tables = _tables()
+    qs = _queries(tables, 12, seed=5)
+    per_query = 2 * 8 * ((5000 + 63) // 64)   # the larger table's two bitvectors
+    ex = HostExecutor(tables)
+    srv = Server(ex, budget_bytes=3 * per_query)
+    res = srv.run(qs)
+    assert len(res) == len(qs)
+    assert max(len(s) for s in ex.steps) <= 3
+    # bitvector reservations never exceed the budget (lookup bytes may, for the oldest query)
+    assert srv.in_use == 0
+    # admission in arrival order
+    adm = [res[q.qid].admitted for q in sorted(qs, key=lambda q: q.qid)]
+    assert adm == sorted(adm)
+
+
+def test_single_query_over_budget_still_runs():
+    tables = _tables()
+    q = _queries(tables, 1, seed=6)[0]
+    res = Server(HostExecutor(tables), budget_bytes=1).run([q])
+    assert res[q.qid].count == _plain(tables, q)[1]
+
+
+def test_late_arrivals_join_between_steps():
+    tables = _tables()
+    clock = FakeClock()
+    arr = [0.0, 0.0, 0.005, 0.5]
+    qs = _queries(tables, 4, seed=7, arrivals=arr)
+    for q in qs:   # three predicates each, so the early queries are still scanning
+        q.preds = (q.preds * 3)[:3]
+    ex = HostExecutor(tables, step_cost=0.01, clock=clock)
+    res = Server(ex, budget_bytes=1 << 30, clock=clock, sleep=clock.sleep).run(qs)
+    # query 2 arrives during the first step and joins at the second
+    assert [len(s) for s in ex.steps[:3]] == [2, 3, 3]
+    assert res[3].admitted >= 0.5
+    assert res[2].admitted == pytest.approx(0.01)
+    for q in qs:
+        assert res[q.qid].count == _plain(tables, q)[1]
+
+
+def test_poisson_and_summary():
+    a = poisson_arrivals(1000, 200.0, seed=9)
+    b = poisson_arrivals(1000, 200.0, seed=9)
+    assert np.array_equal(a, b) and np.all(np.diff(a) >= 0)
+    assert 3.5 < a[-1] < 6.5   # about 1000 / 200 s
+    tables = _tables()
+    res = Server(HostExecutor(tables), budget_bytes=1 << 30).run(_queries(tables, 20, seed=8))
+    s = latency_summary(res)
+    assert s["queries"] == 20 and s["p50_ms"] <= s["p99_ms"]
+
+
+def test_query_without_predicate_rejected():
+    with pytest.raises(ValueError):
+        Server(HostExecutor(_tables()), budget_bytes=1 << 20).run([Query(0, "a", [], ["c0"])])
