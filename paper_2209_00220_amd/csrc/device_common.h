@@ -7,7 +7,7 @@
 //    t*2048 + L*32.  Two 16-byte loads per lane bring a whole tile in, and byte k
 //    of every lane is exactly one 64-row group in row order, so a ballot over a
 //    byte compare is one result word.
-//  * later slices: ByteSlice BS_j dense in row order; PP-VBS BS_j compacted in
+//  * later slices: ByteSlice BS_j tile-interleaved like BS_1; PP-VBS BS_j compacted in
 //    row order (only rows with a j-th byte), bitmask M_j one uint64 per 64 rows,
 //    directory DIR_j = running count of j-th bytes every 2^dir_shift rows.
 //  * Bit-Packed: in tile t, lane L's 32 codes packed LSB first into w dwords;
@@ -291,6 +291,25 @@ __device__ __forceinline__ uint32_t stage_run(const uint8_t* __restrict__ src, u
     return (uint32_t)(start - a);
 }
 
+// The length rule of a level on lane-held words (32 rows per lane dword): rows
+// still equal to the literal (plov / phiv) either have a next byte (m) or end.
+// Returns the rows newly found in the tracked relation; klo / khi are all ones
+// while the level is shorter than the lower / upper literal.
+template <int MODE>
+__device__ __forceinline__ uint32_t level_mask_vec(uint32_t& plov, uint32_t& phiv, uint32_t m, uint32_t klo,
+                                                   uint32_t khi) {
+    uint32_t hit;
+    if (MODE == kModeLT || MODE == kModeBetween) hit = plov & ~m & klo;   // a proper prefix: below
+    else if (MODE == kModeGT) hit = plov & m & ~klo;                     // equal, then more bytes: above
+    else hit = plov & ~m & ~klo;                                         // equal over the whole literal
+    plov &= m & klo;
+    if (MODE == kModeBetween) {
+        hit |= phiv & m & ~khi;
+        phiv &= m & khi;
+    }
+    return hit;
+}
+
 // One tile, one wave.
 //
 // Byte 1: for each of the 32 groups (unrolled, the tile is in registers) the
@@ -362,15 +381,7 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
     // byte 2's presence settles the rows equal on byte 1 that end there
     {
         const uint32_t m2v = DENSE ? (K >= 2 ? ~0u : 0u) : td.m2;
-        uint32_t hit;
-        if (MODE == kModeLT || MODE == kModeBetween) hit = plov & ~m2v & klo;   // a proper prefix: below
-        else if (MODE == kModeGT) hit = plov & m2v & ~klo;                     // equal, then more bytes: above
-        else hit = plov & ~m2v & ~klo;                                         // equal over the whole literal
-        plov &= m2v & klo;
-        if (MODE == kModeBetween) {
-            hit |= phiv & m2v & ~khi;
-            phiv &= m2v & khi;
-        }
+        const uint32_t hit = level_mask_vec<MODE>(plov, phiv, m2v, klo, khi);
         outv = MODE == kModeBetween ? (outv & ~hit) : (outv | hit);
     }
     // later bytes, pending groups only
@@ -378,6 +389,47 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
     // compile time so the later-byte code drops out
     constexpr bool kByte1Only = MODE == kModeBetween ? (kLoShort && kHiShort) : kLoShort;
     uint32_t pend = kByte1Only ? 0u : group_mask(plov | phiv);
+    if constexpr (DENSE) {
+        // ByteSlice: every row has every byte and slice j is tile-interleaved like
+        // slice 1, so byte j of the tile is one 2 KB read into the same lane layout
+        // and a level settles all pending groups with compares and lane writes
+        for (uint32_t j = 2; pend != 0 && j <= K; ++j) {
+            if (COUNT) {
+                if (j == 2) st.deep_groups += __builtin_popcount(pend);
+                st.alg += 64ull * __builtin_popcount(pend);
+                st.rowbytes += wave_sum(__builtin_popcount(plov | phiv), lane);
+            }
+            const auto rj = buffer_rsrc(c.bs[j] + t * kTileRows, kTileRows);
+            const uint4 a0 = buffer_load16(rj, lane * 32), a1 = buffer_load16(rj, lane * 32 + 16);
+            const uint32_t bw[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+            const uint32_t cjlo = lit_byte(lit.lo, j), cjhi = lit_byte(lit.hi, j);
+            uint32_t xq[2] = {0, 0}, eq[2] = {0, 0}, yq[2] = {0, 0}, fq[2] = {0, 0};
+            Unroll<0, 32>::run([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                if ((pend >> k) & 1u) {
+                    const uint32_t b = (bw[k >> 2] >> (8 * (k & 3))) & 0xffu;
+                    // xq: rows leaving the lower literal's tie in the tracked direction
+                    if (MODE == kModeLT || MODE == kModeBetween) xq[k & 1] = put_word_at(xq[k & 1], k, ballot(b < cjlo));
+                    if (MODE == kModeGT) xq[k & 1] = put_word_at(xq[k & 1], k, ballot(b > cjlo));
+                    eq[k & 1] = put_word_at(eq[k & 1], k, ballot(b == cjlo));
+                    if (MODE == kModeBetween) {
+                        yq[k & 1] = put_word_at(yq[k & 1], k, ballot(b > cjhi));
+                        fq[k & 1] = put_word_at(fq[k & 1], k, ballot(b == cjhi));
+                    }
+                }
+            });
+            uint32_t hit = MODE == kModeEQ ? 0u : (plov & (xq[0] | xq[1]));
+            plov &= eq[0] | eq[1];
+            if (MODE == kModeBetween) {
+                hit |= phiv & (yq[0] | yq[1]);
+                phiv &= fq[0] | fq[1];
+            }
+            hit |= level_mask_vec<MODE>(plov, phiv, j < K ? ~0u : 0u, j < lit.llo ? ~0u : 0u, j < lit.lhi ? ~0u : 0u);
+            outv = MODE == kModeBetween ? (outv & ~hit) : (outv | hit);
+            pend = group_mask(plov | phiv);
+        }
+        pend = 0;
+    }
     uint32_t cur_mv = DENSE ? 0u : td.m2;   // this lane's dword of the tile's M_j words
     for (uint32_t j = 2; pend != 0 && j <= K; ++j) {
         if (COUNT && j == 2) st.deep_groups += __builtin_popcount(pend);
@@ -650,7 +702,7 @@ __device__ __forceinline__ uint32_t lookup_row(const DevCol& c, uint64_t r) {
     }
     if (c.layout == BST_BYTESLICE) {
         uint64_t v = c.bs[1][pos1];
-        for (uint32_t j = 2; j <= c.K; ++j) v = (v << 8) | c.bs[j][r];
+        for (uint32_t j = 2; j <= c.K; ++j) v = (v << 8) | c.bs[j][pos1];
         const uint32_t code = (uint32_t)(v >> (8 * c.K - c.width));
         return c.domain_mode ? code : c.dict[code];
     }

@@ -309,8 +309,11 @@ static void build_byteslice(HostColumn& c, const uint32_t* vals, uint32_t T) {
     parallel_chunks(n, T, kTileRows, [&](uint64_t lo, uint64_t hi, uint32_t) {
         for (uint64_t r = lo; r < hi; ++r) {
             uint64_t v = (uint64_t)vals[r] << (8 * K - w);
-            c.buf[BST_BUF_BS1][bs1_pos(r)] = (uint8_t)(v >> (8 * (K - 1)));
-            for (uint32_t j = 2; j <= K; ++j) c.buf[BST_BUF_BS2 + j - 2][r] = (uint8_t)(v >> (8 * (K - j)));
+            // every slice tile-interleaved like BS_1, so a tile's byte j comes into
+            // registers in the same lane layout as its byte 1
+            const uint64_t pos = bs1_pos(r);
+            c.buf[BST_BUF_BS1][pos] = (uint8_t)(v >> (8 * (K - 1)));
+            for (uint32_t j = 2; j <= K; ++j) c.buf[BST_BUF_BS2 + j - 2][pos] = (uint8_t)(v >> (8 * (K - j)));
         }
     });
 }
@@ -713,10 +716,11 @@ int bst_host_paper_view(const bst_host_column* hc, int part, int j, void* out, u
         *bytes = len;
         if (!out) return BST_OK;
         uint8_t* o = (uint8_t*)out;
-        if (j == 1)
-            for (uint64_t r = 0; r < n; ++r) o[r] = c.buf[BST_BUF_BS1][bs1_pos(r)];
+        const uint8_t* src = c.buf[j == 1 ? BST_BUF_BS1 : BST_BUF_BS2 + j - 2].data();
+        if (j == 1 || c.layout == BST_BYTESLICE)   // tile-interleaved slices back to row order
+            for (uint64_t r = 0; r < n; ++r) o[r] = src[bs1_pos(r)];
         else
-            memcpy(o, c.buf[BST_BUF_BS2 + j - 2].data(), len);
+            memcpy(o, src, len);
         return BST_OK;
     }
     if (part == 1) {
