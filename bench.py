@@ -161,9 +161,174 @@ def serve_bench(dev_cols, x_counts, n_queries: int, budget_bytes: int):
     }
 
 
+def _ms_events(fn, repeats=5):
+    """Median milliseconds of fn() between HIP events on the current stream."""
+    import numpy as np
+    import torch
+
+    fn()
+    ts = []
+    for _ in range(repeats):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def wide_main(args):
+    """Wide table: per-column layout advice (Algorithm 5), a pipelined four-column
+    conjunction in the chosen layouts, and lookups of three columns on its rows."""
+    import numpy as np
+    import torch
+
+    from datagen import workloads
+    from paper_2209_00220_amd.advisor import advise_column
+    from paper_2209_00220_amd.column import bv_compact, bv_popcount, bv_to_numpy, nwords, u32_to_numpy
+
+    n = args.wide_rows
+    torch.cuda.set_device(0)
+    xs, adv = {}, {}
+    t_adv = 0.0
+    for c in range(16):
+        x, w = workloads.config3_column(c, n)
+        xs[c] = x
+        progress("column %d: w=%d s=%.1f -- advisor over 3 layouts" % (c, w, workloads.WIDE_SKEWS[c % 4]))
+        t0 = time.time()
+        a = advise_column(x, numeric=True, width=w, layouts=("byteslice", "ppvbs", "bitpacked"), keep="all")
+        t_adv += time.time() - t0
+        adv[c] = a
+        progress("  chose %s, AUC %s" % (a.chosen, {k: round(v, 4) for k, v in a.aucs.items()}))
+    # the query: '<' at about 31.6 % on each filter column, pipelined
+    lits = {}
+    for c in workloads.WIDE_FILTER:
+        v, k = workloads.value_counts(xs[c], workloads.WIDE_WIDTHS[c % 6])
+        lits[c] = workloads.lit_lt(v, k, 0.316)[0]
+    bvs = [torch.empty(nwords(n), dtype=torch.int64, device="cuda") for _ in range(2)]
+
+    def conj(choice):
+        cur = None
+        for i, c in enumerate(workloads.WIDE_FILTER):
+            col = adv[c].columns[choice(c)][1]
+            col.scan("lt", lits[c], in_mask=cur, out=bvs[i % 2])
+            cur = bvs[i % 2]
+        return cur
+
+    res = {}
+    for name, choice in (("advised", lambda c: adv[c].chosen), ("ppvbs", lambda c: "ppvbs"),
+                         ("byteslice", lambda c: "byteslice"), ("bitpacked", lambda c: "bitpacked")):
+        ms = _ms_events(lambda: conj(choice))
+        res[name] = {"conjunction_ms": round(ms, 3), "gtuples": round(4 * n / (ms * 1e-3) / 1e9, 1)}
+    sel_bv = conj(lambda c: adv[c].chosen)
+    count = int(bv_popcount(sel_bv, n).item())
+    want = np.ones(n, dtype=bool)
+    for c in workloads.WIDE_FILTER:
+        want &= xs[c] < np.uint32(lits[c])
+    assert count == int(want.sum()), "conjunction count differs from the plain one"
+    ids, _ = bv_compact(sel_bv, n, max(count, 1))
+    look = {}
+    for c in workloads.WIDE_LOOKUP:
+        col = adv[c].columns[adv[c].chosen][1]
+        out_v = torch.empty(max(count, 1), dtype=torch.int32, device="cuda")
+        ms = _ms_events(lambda: col.lookup(ids[:count], out=out_v[:count]))
+        got = u32_to_numpy(out_v[:count])
+        assert np.array_equal(got, xs[c][want]), "lookup differs from the raw values"
+        look[c] = {"layout": adv[c].chosen, "ms": round(ms, 3), "mrows": round(count / (ms * 1e-3) / 1e6, 1)}
+    out = {
+        "metric": "wide-table conjunction Gtuples/s (advised layouts) and lookup Mrows/s",
+        "value": res["advised"]["gtuples"], "unit": "Gtuples/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "16 columns x %d rows; '<' on columns 2,5,7,9 (~31.6%% each) pipelined; "
+                               "lookup of columns 0,10,11 on the qualifying rows" % n, "rows": n},
+        "advisor": {str(c): {"chosen": adv[c].chosen, "auc": {k: round(v, 5) for k, v in adv[c].aucs.items()},
+                             "w": workloads.WIDE_WIDTHS[c % 6], "s": workloads.WIDE_SKEWS[c % 4]} for c in adv},
+        "advisor_seconds": round(t_adv, 1),
+        "conjunction": res, "qualifying_rows": count, "lookups": {str(k): v for k, v in look.items()},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def batch_main(args):
+    """Many scans over many columns: one persistent launch (HIP graph, autotuned
+    shape) against one launch per predicate."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from datagen import workloads
+    from paper_2209_00220_amd.batch import Batch, autotune, time_call
+    from paper_2209_00220_amd.column import DeviceColumn, Dictionary, HostColumn, bv_popcount
+
+    torch.cuda.set_device(0)
+    specs = workloads.config4_columns(args.batch_cols)
+    cols, counts, keep = [], [], []
+    for i, (n, w, s, seed) in enumerate(specs):
+        x = datagen.zipf_column(n, w, s, seed=seed)
+        counts.append(workloads.value_counts(x, w))
+        d = Dictionary(x)
+        hc = HostColumn.encode(d, "ppvbs")
+        d.close()
+        cols.append(DeviceColumn(hc))
+        keep.append(hc)
+        del x
+        if i % 8 == 7:
+            progress("encoded %d / %d columns" % (i + 1, len(specs)))
+    preds = workloads.config4_predicates(counts, args.batch_preds)
+    outs = [cols[c].new_bv() for c, *_ in preds]
+    rows = sum(int(cols[c].n_rows) for c, *_ in preds)
+    alg = 0
+    for (c, op, lo, hi, _), o in zip(preds, outs):
+        _, ctr = cols[c].scan_stats(op, lo, hi, out=o)
+        alg += int(ctr[0].item())
+
+    def singles():
+        for (c, op, lo, hi, _), o in zip(preds, outs):
+            cols[c].scan(op, lo, hi, out=o)
+
+    single_ms = _ms_events(singles)
+    b = Batch([(cols[c], op, lo, hi, None) for c, op, lo, hi, _ in preds], outs)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    best, table = autotune(b, grids=[cus * 4, cus * 8, cus * 16], grabs=(8, 16, 32, 64), repeats=3)
+    batch_ms = time_call(lambda: b.launch(best[0], best[1], True), repeats=5)
+    torch.cuda.synchronize()
+    # every result's popcount against the plain count from the value counts
+    for (c, op, lo, hi, _), o in zip(preds, outs):
+        v, k = counts[c]
+        if op == "lt":
+            want = int(k[v < lo].sum())
+        elif op == "le":
+            want = int(k[v <= lo].sum())
+        elif op == "eq":
+            want = int(k[v == lo].sum())
+        else:
+            want = int(k[(v >= lo) & (v <= hi)].sum())
+        assert int(bv_popcount(o, int(cols[c].n_rows)).item()) == want, (c, op, lo, hi)
+    out = {
+        "metric": "batched scans Gtuples/s (one persistent launch vs one launch per predicate)",
+        "value": round(rows / (batch_ms * 1e-3) / 1e9, 1), "unit": "Gtuples/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "%d PP-VBS columns (n log-uniform in [1e6, 1e8], w in 8..32, Zipf s in [0, 1.5]); "
+                               "%d predicates (<, <=, =, BETWEEN; selectivity log-uniform 0.01-50%%)"
+                               % (len(specs), len(preds)), "rows_scanned": rows},
+        "batch_ms": round(batch_ms, 3), "single_launches_ms": round(single_ms, 3),
+        "speedup": round(single_ms / batch_ms, 3), "grid": best[0], "tiles_per_grab": best[1],
+        "alg_bytes": alg, "batch_hbm_frac": round(alg / (batch_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "single_gtuples": round(rows / (single_ms * 1e-3) / 1e9, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=("scan", "wide", "batch"), default="scan",
+                    help="scan: the one-column benchmark (default); wide: 16-column table with the advisor, "
+                         "a conjunction and lookups; batch: 256 predicates over 64 columns in one launch")
+    ap.add_argument("--wide-rows", type=int, default=100_000_000)
+    ap.add_argument("--batch-cols", type=int, default=64)
+    ap.add_argument("--batch-preds", type=int, default=256)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--rows", type=int, default=500_000_000)
@@ -178,6 +343,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (a plain copy kernel to scale memory counters)")
     args = ap.parse_args()
+    if args.workload != "scan":
+        if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+            print("bench.py measures one GPU; run with --gpus 1", file=sys.stderr)
+            sys.exit(2)
+        (wide_main if args.workload == "wide" else batch_main)(args)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

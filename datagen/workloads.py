@@ -87,3 +87,54 @@ def config2(n: int = 500_000_000, threads=None, n_ids: int | None = None):
     m = n_ids if n_ids is not None else max(1, n // 100)
     ids = uniform_ids(m, n, seed=1)
     return {"x": x, "w": 20, "preds": preds, "ids": ids}
+
+
+# config3: a wide table -- 16 columns of n rows; column c has width
+# [8, 12, 16, 20, 24, 32][c % 6] and Zipf exponent [0, 0.5, 1.0, 1.5][c % 4]
+# (0 = uniform), seed c.  The query pipelines '<' on columns 2, 5, 7, 9, each at
+# about 31.6 % selectivity (about 1 % together), and looks up columns 0, 10, 11
+# on the qualifying rows.
+WIDE_WIDTHS = (8, 12, 16, 20, 24, 32)
+WIDE_SKEWS = (0.0, 0.5, 1.0, 1.5)
+WIDE_FILTER = (2, 5, 7, 9)
+WIDE_LOOKUP = (0, 10, 11)
+
+
+def config3_column(c: int, n: int, threads=None):
+    w = WIDE_WIDTHS[c % 6]
+    return zipf_column(n, w, WIDE_SKEWS[c % 4], seed=c, threads=threads), w
+
+
+# config4: 64 columns, n_c = exp(U[ln 1e6, ln 1e8]), w_c ~ U{8..32},
+# s_c ~ U[0, 1.5]; 256 predicates: column ~ U, op ~ U{<, <=, =, BETWEEN},
+# selectivity log-uniform in [0.01 %, 50 %] (the nearest reachable one).
+def config4_columns(n_cols: int = 64, seed: int = 4, n_lo: float = 1e6, n_hi: float = 1e8):
+    rng = np.random.default_rng(seed)
+    specs = []
+    for c in range(n_cols):
+        n = int(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        w = int(rng.integers(8, 33))
+        s = float(rng.uniform(0.0, 1.5))
+        specs.append((n, w, s, 100 + c))
+    return specs
+
+
+def config4_predicates(counts, n_preds: int = 256, seed: int = 5):
+    """counts: per column (values, counts); returns [(column, op, lo, hi, selectivity)]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_preds):
+        c = int(rng.integers(0, len(counts)))
+        v, k = counts[c]
+        op = ("lt", "le", "eq", "between")[int(rng.integers(0, 4))]
+        sel = float(np.exp(rng.uniform(np.log(1e-4), np.log(0.5))))
+        if op in ("lt", "le"):
+            lo, got = lit_lt(v, k, sel)
+            out.append((c, op, lo, None, got))
+        elif op == "eq":
+            lo, got = lit_eq(v, k, sel)
+            out.append((c, op, lo, None, got))
+        else:
+            lo, hi, got = lit_between(v, k, sel)
+            out.append((c, op, lo, hi, got))
+    return out

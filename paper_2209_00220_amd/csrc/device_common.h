@@ -726,7 +726,7 @@ struct BatchItem {
     const uint64_t* in_mask;
     uint64_t* out;
     uint64_t tile0;   // first global tile of this item
-    uint32_t kind;    // dispatch code, see batch_kind()
+    uint32_t kind;    // dispatch code: see batch_kind()
     uint32_t pad;
 };
 
@@ -749,6 +749,9 @@ __device__ __forceinline__ uint32_t batch_find(const BatchItem* __restrict__ ite
 using BatchKernel = void (*)(const BatchHeader*, const BatchItem*, unsigned long long*, uint32_t);
 // Persistent Bit-Packed batch kernel for code width w (nullptr outside 1..32).
 BatchKernel batch_packed_kernel(uint32_t w, bool has_in);
+// Persistent slice-layout batch kernel for one-byte literals; mi: 0 '<', 1 '>',
+// 2 '=', 3 BETWEEN.
+BatchKernel batch_short_kernel(int mi, bool dense, bool has_in);
 
 
 // ------------------------------------------------------------ host helpers

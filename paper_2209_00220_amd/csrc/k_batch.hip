@@ -1,7 +1,7 @@
 // Batched scans: many predicates over many columns in one persistent launch.
 #include <vector>
 
-#include "device_common.h"
+#include "batch_kernel.h"
 
 using namespace bst;
 using namespace bst::dev;
@@ -11,37 +11,8 @@ namespace dev {
 
 // Items of one group share a kernel variant (layout, operator or width, incoming
 // mask or not); tile0 counts tiles within the group.
-constexpr int kBatchGroupsMax = 2 * (4 * 2 + 32);   // (4 modes x 2 slice layouts + 32 widths) x in/out
+constexpr int kBatchGroupsMax = 2 * (16 + 32);   // (16 slice kinds + 32 widths) x with/without incoming mask
 constexpr uint64_t kBatchHeaderBytes = 64;          // per group: BatchHeader, then the grab counter at +32
-
-// Waves take `grab` consecutive tiles of the group's concatenated tile list at a
-// time and scan them item by item (a grab may straddle items); the per-tile
-// work is the single-column scan's, inlined.
-template <int MODE, bool DENSE, bool HAS_IN>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMinWaves, 8))) void k_batch_slices(
-    const BatchHeader* __restrict__ hdr, const BatchItem* __restrict__ items, unsigned long long* __restrict__ counter,
-    uint32_t grab) {
-    __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerBlock][kStageBytes];
-    uint8_t* lds = stage[threadIdx.x >> 6];
-    const uint32_t lane = threadIdx.x & 63;
-    const uint64_t total = hdr->total_tiles;
-    const uint32_t n_items = hdr->n_items;
-    Stats st;
-    for (;;) {
-        uint64_t start = 0;
-        if (lane == 0) start = atomicAdd(counter, (unsigned long long)grab);
-        start = ((uint64_t)uniform((uint32_t)(start >> 32)) << 32) | uniform((uint32_t)start);
-        if (start >= total) break;
-        const uint64_t stop = std::min<uint64_t>(total, start + grab);
-        for (uint32_t cur = batch_find(items, n_items, start); cur < n_items && items[cur].tile0 < stop; ++cur) {
-            const BatchItem& it = items[cur];
-            const uint64_t b0 = std::max<uint64_t>(start, it.tile0) - it.tile0;
-            const uint64_t b1 = std::min<uint64_t>(stop, it.tile0 + it.c.ntiles) - it.tile0;
-            scan_slices_range<MODE, -1, DENSE, HAS_IN, false>(it.c, it.lit, it.in_mask, it.out, b0, b1, 1, lane, lds,
-                                                               st);
-        }
-    }
-}
 
 // Zero the groups' grab counters (a fill kernel, so the launch sequence can be
 // captured in a graph).
@@ -56,9 +27,10 @@ static BatchKernel batch_kernel(uint32_t kind, bool has_in) {
     if (kind < 16) {
         const bool dense = kind & 1;
         const int mi = (kind >> 1) & 3;
-#define BST_K(MODE)                                                                              \
-    return dense ? (has_in ? k_batch_slices<MODE, true, true> : k_batch_slices<MODE, true, false>) \
-                 : (has_in ? k_batch_slices<MODE, false, true> : k_batch_slices<MODE, false, false>)
+        if (kind & 8) return batch_short_kernel(mi, dense, has_in);
+#define BST_K(MODE)                                                                                        \
+    return dense ? (has_in ? k_batch_slices<MODE, -1, true, true> : k_batch_slices<MODE, -1, true, false>) \
+                 : (has_in ? k_batch_slices<MODE, -1, false, true> : k_batch_slices<MODE, -1, false, false>)
         switch (mi) {
             case 0: BST_K(kModeLT);
             case 1: BST_K(kModeGT);

@@ -213,7 +213,9 @@ int run_scan(const bst_column* col, const ScanLit& lit, const uint64_t* in, uint
 uint32_t batch_kind(const bst_column* col, const ScanLit& lit) {
     if (col->dev.layout == BST_BITPACKED) return 16 + col->dev.width;
     int mi = lit.mode == kModeLT ? 0 : lit.mode == kModeGT ? 1 : lit.mode == kModeEQ ? 2 : 3;
-    return (uint32_t)((col->dev.layout == BST_BYTESLICE ? 1 : 0) | (mi << 1));
+    // bit 3: every literal is one byte long, so byte 1 and M_2 settle every row
+    const bool one = lit.llo == 1 && (lit.mode != kModeBetween || lit.lhi == 1);
+    return (uint32_t)((col->dev.layout == BST_BYTESLICE ? 1 : 0) | (mi << 1) | (one ? 8 : 0));
 }
 
 }  // namespace dev
