@@ -450,10 +450,12 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
         const uint32_t cjlo = lit_byte(lit.lo, j), cjhi = lit_byte(lit.hi, j);
         uint32_t pend_next = 0;
         if (staged) {
-            // the run is in LDS: walk the groups at compile-time positions, eight
-            // at a time, all eight LDS reads issued before the first compare
+            // the run is in LDS: read the pending groups' bytes at compile-time
+            // group positions (eight reads in flight), compare into lane words,
+            // and settle the level for the whole tile with vector operations
             const uint32_t sh = stage_run(c.bs[j], run0, runlen, lds, lane);
-            if (COUNT) st.alg += DENSE ? 64ull * __builtin_popcount(pend) : 0ull;
+            if (COUNT) st.rowbytes += wave_sum(__builtin_popcount(plov | phiv), lane);
+            uint32_t xq[2] = {0, 0}, eq[2] = {0, 0}, yq[2] = {0, 0}, fq[2] = {0, 0};
             Unroll<0, 4>::run([&](auto cc) {
                 constexpr int c8 = decltype(cc)::value * 8;
                 if ((pend >> c8) & 0xffu) {
@@ -476,33 +478,30 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
                     Unroll<0, 8>::run([&](auto ic) {
                         constexpr int i = decltype(ic)::value, k = c8 + i;
                         if ((pend >> k) & 1u) {
-                            uint64_t plo = lane_word(plov, k);
-                            uint64_t phi = MODE == kModeBetween ? lane_word(phiv, k) : 0ull;
-                            if (COUNT) st.rowbytes += __builtin_popcountll(plo | phi);
-                            uint64_t hit = 0;
-                            byte_step<MODE>(plo, phi, hit, bb[i], cjlo, cjhi);
-                            if ((plo | phi) != 0) {
-                                uint64_t m = 0;
-                                if (j < K) {
-                                    if (DENSE) {
-                                        m = ~0ull;
-                                    } else {
-                                        m = lane_word(next_mv, k);
-                                        if (COUNT) st.alg += 8;
-                                    }
-                                }
-                                level_step<MODE>(plo, phi, hit, m, j, lit.llo, lit.lhi);
-                            }
-                            if (hit) outv = put_word_at(outv, k, apply_hit<MODE>(lane_word(outv, k), hit));
-                            if ((plo | phi) != 0) {
-                                pend_next |= 1u << k;
-                                plov = put_word_at(plov, k, plo);
-                                if (MODE == kModeBetween) phiv = put_word_at(phiv, k, phi);
+                            const uint32_t bj = bb[i];
+                            if (MODE == kModeLT || MODE == kModeBetween)
+                                xq[k & 1] = put_word_at(xq[k & 1], k, ballot(bj < cjlo));
+                            if (MODE == kModeGT) xq[k & 1] = put_word_at(xq[k & 1], k, ballot(bj > cjlo));
+                            eq[k & 1] = put_word_at(eq[k & 1], k, ballot(bj == cjlo));
+                            if (MODE == kModeBetween) {
+                                yq[k & 1] = put_word_at(yq[k & 1], k, ballot(bj > cjhi));
+                                fq[k & 1] = put_word_at(fq[k & 1], k, ballot(bj == cjhi));
                             }
                         }
                     });
                 }
             });
+            uint32_t hit = MODE == kModeEQ ? 0u : (plov & (xq[0] | xq[1]));
+            plov &= eq[0] | eq[1];
+            if (MODE == kModeBetween) {
+                hit |= phiv & (yq[0] | yq[1]);
+                phiv &= fq[0] | fq[1];
+            }
+            const uint32_t mnext = j < K ? (DENSE ? ~0u : next_mv) : 0u;
+            if (COUNT && !DENSE && j < K) st.alg += 8ull * __builtin_popcount(group_mask(plov | phiv));
+            hit |= level_mask_vec<MODE>(plov, phiv, mnext, j < lit.llo ? ~0u : 0u, j < lit.lhi ? ~0u : 0u);
+            outv = MODE == kModeBetween ? (outv & ~hit) : (outv | hit);
+            pend_next = group_mask(plov | phiv);
             pend = 0;
         }
         while (pend) {
@@ -558,11 +557,10 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
                         level_step<MODE>(plo, phi, hit, m, j, lit.llo, lit.lhi);
                     }
                     if (hit) outv = put_word_at(outv, k, apply_hit<MODE>(lane_word(outv, k), hit));
-                    if ((plo | phi) != 0) {
-                        pend_next |= 1u << k;
-                        plov = put_word_at(plov, k, plo);
-                        if (MODE == kModeBetween) phiv = put_word_at(phiv, k, phi);
-                    }
+                    // written back even when settled: the lane words stay exact for the next level
+                    plov = put_word_at(plov, k, plo);
+                    if (MODE == kModeBetween) phiv = put_word_at(phiv, k, phi);
+                    if ((plo | phi) != 0) pend_next |= 1u << k;
                 }
             }
         }
