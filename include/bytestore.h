@@ -288,10 +288,15 @@ int bst_batch_prepare(const bst_column* const* cols, const bst_pred* preds,
                       const uint64_t* const* in_masks, uint64_t* const* outs, int n_items,
                       void* workspace, bst_batch** out);
 /*
- * Run every scan of the batch in one persistent launch: `grid` workgroups
- * (0 = tuned default) take `tiles_per_grab` tiles at a time from a shared
- * queue.  With use_graph != 0 the launch sequence is captured once into a HIP
- * graph and replayed on later calls with the same grid and grab size.
+ * Run every scan of the batch: items are grouped by kernel variant (layout,
+ * operator or code width, one-byte literal, incoming mask), and each group is
+ * one persistent launch of `grid` workgroups (0 = tuned default) whose waves
+ * take at least `tiles_per_grab` (0 = tuned default) consecutive 2048-row tiles
+ * at a time from the group's queue -- more when the group is large, so that a
+ * wave takes about four times per group.  With use_graph != 0 the launch
+ * sequence is captured once into a HIP graph and replayed on later calls with
+ * the same grid and grab size.  Errors: BST_EINVAL for a NULL batch, BST_EHIP
+ * for a failed launch or capture.
  */
 int bst_batch_launch(bst_batch* b, uint32_t grid, uint32_t tiles_per_grab, int use_graph,
                      void* stream);

@@ -618,47 +618,86 @@ struct PackedLit {
     uint32_t a, span, negate, none;
 };
 
-template <int W, bool HAS_IN>
-__device__ __forceinline__ void scan_packed_tile(const DevCol& c, const PackedLit& pl,
-                                                 const uint64_t* __restrict__ in_mask,
-                                                 uint64_t* __restrict__ out, uint64_t t, uint32_t lane,
-                                                 uint64_t& alg) {
-    const uint64_t w0 = t * 32;
-    uint32_t* out32 = reinterpret_cast<uint32_t*>(out);
-    const uint64_t nwords = (c.n + 63) >> 6;
-    if (HAS_IN) {
-        const uint64_t d = w0 * 2 + lane;
-        const uint32_t mine = d < nwords * 2 ? reinterpret_cast<const uint32_t*>(in_mask)[d] : 0u;
-        if (ballot(mine != 0) == 0) {
-            if (d < nwords * 2) out32[d] = 0;
-            alg += 512;
-            return;
-        }
-    }
-    const uint32_t* base = c.packed + t * 64 * W + lane;
+// Registers of one Bit-Packed tile: lane L's w dwords and its incoming-mask dword.
+template <int W>
+struct PackedTile {
     uint32_t v[W];
+    uint32_t in;
+};
+
+// Loads of tile t (zeros, and no memory read, when `valid` is false).
+template <int W, bool HAS_IN>
+__device__ __forceinline__ PackedTile<W> load_packed(const DevCol& c, const uint64_t* __restrict__ in_mask,
+                                                     uint64_t t, uint32_t lane, bool valid) {
+    PackedTile<W> p;
+    const auto r = buffer_rsrc(c.packed + (valid ? t * 64 * W : 0), valid ? 256u * W : 0u);
 #pragma unroll
-    for (int i = 0; i < W; ++i) v[i] = base[i * 64];
+    for (int i = 0; i < W; ++i) p.v[i] = buffer_load4(r, (uint32_t)(i * 64 + lane) * 4);
+    p.in = ~0u;
+    if (HAS_IN) {
+        const uint64_t nd = ((c.n + 63) >> 6) * 2, d0 = t * 64;
+        const uint32_t avail = (valid && d0 < nd) ? (uint32_t)(nd - d0 < 64 ? nd - d0 : 64) * 4u : 0u;
+        const void* base = avail ? (const void*)(reinterpret_cast<const uint32_t*>(in_mask) + d0) : (const void*)in_mask;
+        p.in = buffer_load4(buffer_rsrc(base, avail), lane * 4);
+    }
+    return p;
+}
+
+// One tile: per group the range test's ballot goes into lanes 2k, 2k+1 of the
+// result dwords; the incoming mask, the column's end and negation are applied
+// lane-parallel before the 256-byte store.
+template <int W, bool HAS_IN>
+__device__ __forceinline__ void process_packed(const DevCol& c, const PackedLit& pl, uint64_t* __restrict__ out,
+                                               uint64_t t, uint64_t t_end, uint32_t lane, const PackedTile<W>& p,
+                                               uint64_t& alg) {
+    if (t >= t_end) return;
+    const uint64_t d = t * 64 + lane;
+    const bool full = (t + 1) * kTileRows <= c.n;
+    uint32_t actv = p.in;
+    if (!full) {
+        const uint64_t r0 = d * 32;
+        actv &= r0 + 32 <= c.n ? ~0u : (r0 < c.n ? (1u << (c.n - r0)) - 1u : 0u);
+    }
     alg += 256 * W + 256 + (HAS_IN ? 256 : 0);
-    uint32_t outv = 0;
-    Unroll<0, 32>::run([&](auto kc) {
-        constexpr int k = decltype(kc)::value;
-        constexpr uint32_t kMask = (W == 32) ? 0xffffffffu : ((1u << (W & 31)) - 1u);
-        constexpr int bit = k * W, i = bit >> 5, sh = bit & 31;
-        uint32_t code;
-        if constexpr (sh + W <= 32)
-            code = (v[i] >> sh) & kMask;
-        else
-            code = __builtin_amdgcn_alignbit(v[i + 1], v[i], sh) & kMask;
-        const uint64_t g = w0 + k;
-        uint64_t act = valid_mask(g, c.n);
-        if (HAS_IN) act &= (g < nwords) ? in_mask[g] : 0ull;
-        const uint64_t X = ballot(code - pl.a <= pl.span);
-        const uint64_t res = pl.none ? 0ull : (pl.negate ? (act & ~X) : (act & X));
-        outv = put_word_at(outv, k, res);
-    });
-    const uint64_t d = w0 * 2 + lane;
-    if (d < nwords * 2) out32[d] = outv;
+    uint32_t oq[2] = {0, 0};
+    if (!pl.none) {
+        Unroll<0, 32>::run([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            constexpr uint32_t kMask = (W == 32) ? 0xffffffffu : ((1u << (W & 31)) - 1u);
+            constexpr int bit = k * W, i = bit >> 5, sh = bit & 31;
+            uint32_t code;
+            if constexpr (sh + W <= 32)
+                code = (p.v[i] >> sh) & kMask;
+            else
+                code = __builtin_amdgcn_alignbit(p.v[i + 1], p.v[i], sh) & kMask;
+            oq[k & 1] = put_word_at(oq[k & 1], k, ballot(code - pl.a <= pl.span));
+        });
+    }
+    const uint32_t x = oq[0] | oq[1];
+    const uint32_t outv = pl.none ? 0u : (pl.negate ? (actv & ~x) : (actv & x));
+    if (full || d < ((c.n + 63) >> 6) * 2) reinterpret_cast<uint32_t*>(out)[d] = outv;
+}
+
+// Tiles t_begin, t_begin + stride, ... below t_end; two tiles' registers in
+// ping-pong, so one tile loads while the other is scanned.
+template <int W, bool HAS_IN>
+__device__ __forceinline__ void scan_packed_range(const DevCol& c, const PackedLit& pl,
+                                                  const uint64_t* __restrict__ in_mask, uint64_t* __restrict__ out,
+                                                  uint64_t t_begin, uint64_t t_end, uint64_t stride, uint32_t lane,
+                                                  uint64_t& alg) {
+    if (t_begin >= t_end) return;
+    uint64_t t = t_begin;
+    PackedTile<W> a = load_packed<W, HAS_IN>(c, in_mask, t, lane, true);
+    PackedTile<W> b = load_packed<W, HAS_IN>(c, in_mask, t + stride, lane, t + stride < t_end);
+    const uint64_t mine = (t_end - t_begin + stride - 1) / stride;
+    for (uint64_t i = 0; i < mine; i += 2) {
+        process_packed<W, HAS_IN>(c, pl, out, t, t_end, lane, a, alg);
+        a = load_packed<W, HAS_IN>(c, in_mask, t + 2 * stride, lane, t + 2 * stride < t_end);
+        t += stride;
+        process_packed<W, HAS_IN>(c, pl, out, t, t_end, lane, b, alg);
+        b = load_packed<W, HAS_IN>(c, in_mask, t + 2 * stride, lane, t + 2 * stride < t_end);
+        t += stride;
+    }
 }
 
 // ------------------------------------------------------------ lookup

@@ -153,11 +153,16 @@ static int batch_enqueue(bst_batch* b, uint32_t grid, uint32_t grab, hipStream_t
     }
     if (!b->groups.empty()) {
         hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(128), 0, st, ws, (int)b->groups.size());
+        const uint64_t waves = (uint64_t)grid * kWavesPerBlock;
         for (size_t g = 0; g < b->groups.size(); ++g) {
             const BatchGroup& gr = b->groups[g];
             char* h = ws + g * kBatchHeaderBytes;
+            // at least `grab` tiles per take, and no more than about four takes per
+            // wave: every take is an atomic on the group's one counter
+            const uint64_t fair = (gr.tiles + 4 * waves - 1) / (4 * waves);
+            const uint32_t take = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(grab, fair), 1u << 20);
             hipLaunchKernelGGL(batch_kernel(gr.kind, gr.has_in), dim3(grid), dim3(kBlock), 0, st,
-                               (const BatchHeader*)h, items + gr.first, (unsigned long long*)(h + 32), grab);
+                               (const BatchHeader*)h, items + gr.first, (unsigned long long*)(h + 32), take);
         }
     }
     return hip_check(hipGetLastError(), "batch launch");

@@ -23,8 +23,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_packed(const BatchHeader* __re
             const BatchItem& it = items[cur];
             const uint64_t b0 = std::max<uint64_t>(start, it.tile0) - it.tile0;
             const uint64_t b1 = std::min<uint64_t>(stop, it.tile0 + it.c.ntiles) - it.tile0;
-#pragma nounroll
-            for (uint64_t t = b0; t < b1; ++t) scan_packed_tile<W, HAS_IN>(it.c, it.pl, it.in_mask, it.out, t, lane, alg);
+            scan_packed_range<W, HAS_IN>(it.c, it.pl, it.in_mask, it.out, b0, b1, 1, lane, alg);
         }
     }
 }

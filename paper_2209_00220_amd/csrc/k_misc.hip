@@ -69,32 +69,70 @@ __global__ __launch_bounds__(kBlock) void k_tile_popc(const uint64_t* __restrict
     }
 }
 
-// Exclusive scan of counts[0..ntiles) into offsets[0..ntiles], by one workgroup.
-__global__ __launch_bounds__(1024) void k_scan_offsets(const uint64_t* __restrict__ counts, uint64_t ntiles,
-                                                       uint64_t* __restrict__ offsets,
-                                                       unsigned long long* __restrict__ total_out) {
-    __shared__ uint64_t part[1024];
-    const uint32_t tid = threadIdx.x;
-    const uint64_t per = (ntiles + 1023) / 1024;
-    const uint64_t lo = std::min<uint64_t>(ntiles, tid * per), hi = std::min<uint64_t>(ntiles, lo + per);
-    uint64_t s = 0;
-    for (uint64_t i = lo; i < hi; ++i) s += counts[i];
-    part[tid] = s;
+// Exclusive scan of counts[0..ntiles) into offsets[0..ntiles] in three launches:
+// sums of 1024-count blocks, a scan of those sums in one workgroup, then each
+// block scans its own counts from its sum's offset.  All reads are coalesced.
+constexpr uint32_t kScanBlock = 1024;
+
+// Exclusive scan of v over the workgroup (kScanBlock threads); *total gets the sum.
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t* part, uint64_t* total) {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(incl, o, 64);
+        if ((int)lane >= o) incl += y;
+    }
+    if (lane == 63) part[wave] = incl;
     __syncthreads();
-    for (uint32_t off = 1; off < 1024; off <<= 1) {
-        uint64_t v = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+    if (wave == 0) {
+        uint64_t p = lane < kScanBlock / 64 ? part[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const uint64_t y = __shfl_up(p, o, 64);
+            if ((int)lane >= o) p += y;
+        }
+        if (lane < kScanBlock / 64) part[lane] = p;   // inclusive over waves
     }
-    uint64_t run = part[tid] - s;
-    for (uint64_t i = lo; i < hi; ++i) {
-        offsets[i] = run;
-        run += counts[i];
-    }
-    if (tid == 1023) {
-        offsets[ntiles] = part[1023];
-        if (total_out) *total_out = part[1023];
+    __syncthreads();
+    const uint64_t before = wave ? part[wave - 1] : 0;
+    *total = part[kScanBlock / 64 - 1];
+    return before + incl - v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_block_sums(const uint64_t* __restrict__ counts, uint64_t ntiles,
+                                                           uint64_t* __restrict__ bsum) {
+    __shared__ uint64_t part[kScanBlock / 64];
+    const uint64_t i = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    uint64_t total;
+    block_excl_scan(i < ntiles ? counts[i] : 0, part, &total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// In-place exclusive scan of bsum[0..nb), nb <= 2 * kScanBlock, by one workgroup.
+__global__ __launch_bounds__(kScanBlock) void k_scan_block_sums(uint64_t* __restrict__ bsum, uint32_t nb) {
+    __shared__ uint64_t part[kScanBlock / 64];
+    const uint32_t i0 = 2 * threadIdx.x;
+    const uint64_t a = i0 < nb ? bsum[i0] : 0, b = i0 + 1 < nb ? bsum[i0 + 1] : 0;
+    uint64_t total;
+    const uint64_t ex = block_excl_scan(a + b, part, &total);
+    if (i0 < nb) bsum[i0] = ex;
+    if (i0 + 1 < nb) bsum[i0 + 1] = ex + a;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_offsets(const uint64_t* __restrict__ counts, uint64_t ntiles,
+                                                             const uint64_t* __restrict__ bsum,
+                                                             uint64_t* __restrict__ offsets,
+                                                             unsigned long long* __restrict__ total_out) {
+    __shared__ uint64_t part[kScanBlock / 64];
+    const uint64_t i = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    const uint64_t v = i < ntiles ? counts[i] : 0;
+    uint64_t total;
+    const uint64_t ex = bsum[blockIdx.x] + block_excl_scan(v, part, &total);
+    if (i < ntiles) offsets[i] = ex;
+    if (i + 1 == ntiles) {
+        offsets[ntiles] = ex + v;
+        if (total_out) *total_out = ex + v;
     }
 }
 
@@ -322,12 +360,14 @@ int bst_lookup(const bst_column* col, const uint32_t* row_ids, uint64_t m, uint3
 
 uint64_t bst_compact_workspace_bytes(uint64_t n_rows) {
     const uint64_t nt = (n_rows + kTileRows - 1) / kTileRows;
-    return 8 * (2 * nt + 2);
+    const uint64_t nb = (nt + kScanBlock - 1) / kScanBlock;
+    return 8 * (2 * nt + 2 + nb);
 }
 
 int bst_bv_compact(const uint64_t* bv, uint64_t n_rows, uint32_t* out_ids, uint64_t cap, uint64_t* dev_count,
                    void* workspace, uint32_t* dev_status, void* stream) {
     if (!dev_count || !workspace || (n_rows && !bv) || (cap && !out_ids)) return set_error(BST_EINVAL, "NULL argument");
+    if (n_rows > 0xffffffffull) return set_error(BST_ERANGE, "row IDs are 32-bit: at most 2^32 - 1 rows");
     hipStream_t st = (hipStream_t)stream;
     const uint64_t nt = (n_rows + kTileRows - 1) / kTileRows;
     uint64_t* counts = (uint64_t*)workspace;
@@ -337,7 +377,11 @@ int bst_bv_compact(const uint64_t* bv, uint64_t n_rows, uint32_t* out_ids, uint6
         return hip_check(hipGetLastError(), "compact launch");
     }
     hipLaunchKernelGGL(k_tile_popc, dim3(tile_grid(nt, 0)), dim3(kBlock), 0, st, bv, n_rows, counts, nt);
-    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, st, counts, nt, offsets,
+    const uint64_t nb = (nt + kScanBlock - 1) / kScanBlock;   // at most 2 * kScanBlock (n < 2^32)
+    uint64_t* bsum = offsets + nt + 1;
+    hipLaunchKernelGGL(k_block_sums, dim3((uint32_t)nb), dim3(kScanBlock), 0, st, counts, nt, bsum);
+    hipLaunchKernelGGL(k_scan_block_sums, dim3(1), dim3(kScanBlock), 0, st, bsum, (uint32_t)nb);
+    hipLaunchKernelGGL(k_scan_offsets, dim3((uint32_t)nb), dim3(kScanBlock), 0, st, counts, nt, bsum, offsets,
                        (unsigned long long*)dev_count);
     hipLaunchKernelGGL(k_write_ids, dim3(tile_grid(nt, 0)), dim3(kBlock), 0, st, bv, n_rows, offsets, nt, out_ids, cap,
                        dev_status);

@@ -13,7 +13,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_packed(const DevCol c, const Pa
     const uint32_t wave = uniform(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
     const uint32_t nwaves = gridDim.x * kWavesPerBlock;
     uint64_t alg = 0;
-    for (uint64_t t = wave; t < c.ntiles; t += nwaves) scan_packed_tile<W, HAS_IN>(c, pl, in_mask, out, t, lane, alg);
+    scan_packed_range<W, HAS_IN>(c, pl, in_mask, out, wave, c.ntiles, nwaves, lane, alg);
     if (counters) {
         Stats st;
         st.alg = alg;

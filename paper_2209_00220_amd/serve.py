@@ -68,10 +68,12 @@ class Server:
     """Continuous-batching server.
 
     executor: object with ``n_rows(table)``, ``bv_bytes(table)``, ``new_bv(table)``,
-    ``scan_step(items)``, ``count(table, bv)``, ``lookup(table, column, bv, count)``
-    and ``finish(values)``; ``scan_step`` takes a list of (table, column, op, lo,
-    hi, in_bv or None, out_bv) and returns when every scan has finished, and
-    ``finish`` returns when the lookups that produced ``values`` have.
+    ``scan_step(items)``, ``counts(pairs)``, ``lookup(table, column, bv, count)``
+    and ``finish(values_list)``.  ``scan_step`` takes a list of (table, column,
+    op, lo, hi, in_bv or None, out_bv) and may return before the scans finish
+    (work is ordered on one stream); ``counts`` takes (table, bv) pairs and
+    returns their row counts once known; ``finish`` returns when the lookups
+    that produced the given value dicts have finished.
     budget_bytes: device bytes the admitted queries may hold at once.  A query
     that alone exceeds the budget is still served once nothing else is admitted.
     max_batch: most scans per step.
@@ -139,28 +141,29 @@ class Server:
                 for a in scanning:
                     a.k += 1
                     a.cur, a.nxt = a.nxt, a.cur
-            # finished queries: count, reserve lookup bytes, gather, complete; the
-            # oldest finished query always proceeds, later ones wait for memory
-            still = []
-            first = True
-            for a in active:
-                if a.k < len(a.q.preds):
-                    still.append(a)
-                    continue
-                bv = a.cur
-                count = int(self.ex.count(a.q.table, bv))
-                extra = 8 * count * len(a.q.lookups)
-                if not first and extra and self.in_use + extra > self.budget:
-                    still.append(a)
-                    continue
-                first = False
-                self.in_use += extra
-                self.peak_in_use = max(self.peak_in_use, self.in_use)
-                vals = {c: self.ex.lookup(a.q.table, c, bv, count) for c in a.q.lookups}
-                self.ex.finish(vals)
-                self.in_use -= extra + a.reserved
+            # finished queries: count their rows (one wait for all), reserve lookup
+            # bytes, gather (one wait for all), complete; the oldest finished query
+            # always proceeds, later ones wait for memory
+            finished = [a for a in active if a.k >= len(a.q.preds)]
+            still = [a for a in active if a.k < len(a.q.preds)]
+            if finished:
+                counts = self.ex.counts([(a.q.table, a.cur) for a in finished])
+                gathered = []
+                for i, (a, count) in enumerate(zip(finished, counts)):
+                    extra = 8 * int(count) * len(a.q.lookups)
+                    if i and extra and self.in_use + extra > self.budget:
+                        still.append(a)
+                        continue
+                    self.in_use += extra
+                    self.peak_in_use = max(self.peak_in_use, self.in_use)
+                    vals = {c: self.ex.lookup(a.q.table, c, a.cur, int(count)) for c in a.q.lookups}
+                    gathered.append((a, int(count), extra, vals))
+                self.ex.finish([g[3] for g in gathered])
                 t = self.clock() - t0
-                done[a.q.qid] = Result(a.q.qid, count, vals if keep_values else {}, a.q.arrival, a.admitted, t)
+                for a, count, extra, vals in gathered:
+                    self.in_use -= extra + a.reserved
+                    done[a.q.qid] = Result(a.q.qid, count, vals if keep_values else {}, a.q.arrival, a.admitted, t)
+                still.sort(key=lambda a: a.admitted)
             active = still
         return done
 
@@ -183,9 +186,9 @@ def run_serial(executor, queries: Sequence[Query], keep_values: bool = True,
                 cur = executor.new_bv(q.table)
             executor.scan_step([(q.table, col, op, lo, hi, cur if k > 0 else None, nxt)])
             cur, nxt = nxt, cur
-        count = int(executor.count(q.table, cur))
+        count = int(executor.counts([(q.table, cur)])[0])
         vals = {c: executor.lookup(q.table, c, cur, count) for c in q.lookups}
-        executor.finish(vals)
+        executor.finish([vals])
         done[q.qid] = Result(q.qid, count, vals if keep_values else {}, q.arrival, start, clock() - t0)
     return done
 
@@ -240,6 +243,8 @@ class GpuExecutor:
         return self.torch.empty(self.C.nwords(self._n[table]), dtype=self.torch.int64, device="cuda")
 
     def scan_step(self, items):
+        # enqueued only: later work on the stream is ordered after it, and the
+        # batch's host list lives until its upload (done inside the launch)
         from .batch import Batch
 
         specs = [(self.tables[t][c], op, lo, hi, inb) for t, c, op, lo, hi, inb, _ in items]
@@ -250,16 +255,15 @@ class GpuExecutor:
         else:
             b = Batch(specs, outs)
             b.launch(self.grid, self.grab, use_graph=False)
-            self.torch.cuda.synchronize()
             b.close()
-        self.torch.cuda.synchronize()
 
-    def count(self, table, bv):
-        return int(self.C.bv_popcount(bv, self._n[table]).item())
+    def counts(self, pairs):
+        cs = [self.C.bv_popcount(bv, self._n[t]) for t, bv in pairs]
+        return [int(v) for v in self.torch.cat(cs).cpu().tolist()]
 
     def lookup(self, table, column, bv, count):
         vals, _ = self.tables[table][column].lookup_bv(bv, max(int(count), 1))
         return vals[: int(count)]
 
-    def finish(self, values):
+    def finish(self, values_list):
         self.torch.cuda.synchronize()

@@ -33,13 +33,13 @@ class HostExecutor:
         if self.clock is not None:
             self.clock.t += self.step_cost
 
-    def count(self, t, bv):
-        return int(bv.sum())
+    def counts(self, pairs):
+        return [int(bv.sum()) for _, bv in pairs]
 
     def lookup(self, t, c, bv, count):
         return self.tables[t][c][bv].copy()
 
-    def finish(self, values):
+    def finish(self, values_list):
         pass
 
 
