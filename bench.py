@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Scan / lookup benchmark on one MI355X.
 
-Workload (one step = the whole hot path over one synthetic column):
+Default workload (one step = the whole hot path over one synthetic column):
   one column of 500M rows, Zipf(1.0) over 2^20 values (20-bit codes), stored as
   PP-VBS, ByteSlice (3 slices) and Bit-Packed (20 bits); on each layout the
   scans '<', '=' and BETWEEN at selectivities 0.1, 1, 10, 50, 90 % into a
@@ -12,7 +12,13 @@ Printed: one JSON line.  ``value`` is the PP-VBS scan throughput in Gtuples/s
 (rows scanned / kernel time, inputs resident in HBM); the line also carries
 ByteSlice / Bit-Packed scan and lookup throughputs, the roofline of the PP-VBS
 scan kernel (algorithmic bytes per launch over its HIP-event duration against
-8 TB/s) and the CPU oracle timed on a bounded sample.
+8 TB/s), the same step's scans as one batched launch, a serving run
+(continuous batching vs one query at a time: saturation and p50/p99) and the
+CPU oracle timed on a bounded sample.
+
+Other workloads print their own line: ``--workload wide`` (16-column table:
+layout advisor per column, pipelined conjunction, lookups) and
+``--workload batch`` (256 predicates over 64 columns in one launch).
 """
 from __future__ import annotations
 
