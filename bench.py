@@ -326,12 +326,58 @@ def batch_main(args):
     print(json.dumps(out), flush=True)
 
 
+def sweep_main(args):
+    """Skew and domain sensitivity: per (Zipf s, width w) the bytes per row of each
+    layout and its '<' (about 10 %) and '=' (most frequent value) scan rates."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from datagen import workloads
+    from paper_2209_00220_amd.column import DeviceColumn, Dictionary, HostColumn
+
+    torch.cuda.set_device(0)
+    n = args.sweep_rows
+    rows = []
+    for s in (0.0, 0.5, 1.0, 1.5, 2.0):
+        for w in (4, 8, 12, 16, 20, 24):
+            x = datagen.zipf_column(n, w, s, seed=1000 + int(10 * s) * 100 + w)
+            v, k = workloads.value_counts(x, w)
+            lt = workloads.lit_lt(v, k, 0.10)[0]
+            eq = int(v[int(np.argmax(k))])
+            d = Dictionary(x)
+            rec = {"s": s, "w": w, "distinct": int(v.shape[0])}
+            for lay in LAYOUTS:
+                hc = HostColumn.encode(d, lay, width=0 if lay == "ppvbs" else w)
+                col = DeviceColumn(hc)
+                out = col.new_bv()
+                t_lt = _ms_events(lambda: col.scan("lt", lt, out=out))
+                t_eq = _ms_events(lambda: col.scan("eq", eq, out=out))
+                rec[lay] = {"bits_per_row": round(8 * hc.info.layout_bytes / n, 3),
+                            "lt_gtuples": round(n / (t_lt * 1e-3) / 1e9, 1),
+                            "eq_gtuples": round(n / (t_eq * 1e-3) / 1e9, 1)}
+                col.close()
+                hc.close()
+            d.close()
+            rows.append(rec)
+            progress("s=%.1f w=%d  " % (s, w) + "  ".join(
+                "%s %.1f b/row lt %.0f eq %.0f" % (l, rec[l]["bits_per_row"], rec[l]["lt_gtuples"], rec[l]["eq_gtuples"])
+                for l in LAYOUTS))
+    out = {"metric": "scan Gtuples/s and bits/row per layout across Zipf skew and domain width",
+           "unit": "Gtuples/s", "n_gpus": 1, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "%d rows per column; Zipf s in {0..2}, width w in {4..24}" % n, "rows": n},
+           "points": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("scan", "wide", "batch"), default="scan",
+    ap.add_argument("--workload", choices=("scan", "wide", "batch", "sweep"), default="scan",
                     help="scan: the one-column benchmark (default); wide: 16-column table with the advisor, "
-                         "a conjunction and lookups; batch: 256 predicates over 64 columns in one launch")
+                         "a conjunction and lookups; batch: 256 predicates over 64 columns in one launch; "
+                         "sweep: skew x domain sensitivity of every layout")
+    ap.add_argument("--sweep-rows", type=int, default=50_000_000)
     ap.add_argument("--wide-rows", type=int, default=100_000_000)
     ap.add_argument("--batch-cols", type=int, default=64)
     ap.add_argument("--batch-preds", type=int, default=256)
@@ -353,7 +399,7 @@ def main():
         if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
             print("bench.py measures one GPU; run with --gpus 1", file=sys.stderr)
             sys.exit(2)
-        (wide_main if args.workload == "wide" else batch_main)(args)
+        {"wide": wide_main, "batch": batch_main, "sweep": sweep_main}[args.workload](args)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
