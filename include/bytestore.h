@@ -242,9 +242,17 @@ int bst_lookup_bv(const bst_column* col, const uint64_t* bv, uint32_t* out_value
                   uint64_t* dev_count, uint32_t* ids_tmp, void* workspace, uint32_t* dev_status,
                   void* stream);
 
-/* ---- bitvector helpers (Sec. 2.2: conjunctions of scan results) -------- */
+/* ---- bitvector helpers (Sec. 2.2: conjunctions and disjunctions of scan
+ * results are bitwise operations on their bitvectors) ----------------------
+ * All take ceil(n_rows/64) device words per vector, write `out` (which may
+ * alias an input) with the bits past n_rows cleared, and return BST_EINVAL for
+ * a NULL pointer when n_rows > 0. */
 int bst_bv_and(const uint64_t* a, const uint64_t* b, uint64_t* out, uint64_t n_rows, void* stream);
 int bst_bv_or(const uint64_t* a, const uint64_t* b, uint64_t* out, uint64_t n_rows, void* stream);
+/* out = a AND NOT b */
+int bst_bv_andnot(const uint64_t* a, const uint64_t* b, uint64_t* out, uint64_t n_rows, void* stream);
+/* out = NOT a (within the first n_rows) */
+int bst_bv_not(const uint64_t* a, uint64_t* out, uint64_t n_rows, void* stream);
 /* *dev_count (device uint64) = number of set bits among the first n_rows. */
 int bst_bv_popcount(const uint64_t* bv, uint64_t n_rows, uint64_t* dev_count, void* stream);
 

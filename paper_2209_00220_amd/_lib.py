@@ -81,6 +81,8 @@ _PROTOS = {
     "bst_lookup_bv": (_I, [_P, _P, _P, _U64, _P, _P, _P, _P, _P]),
     "bst_bv_and": (_I, [_P, _P, _P, _U64, _P]),
     "bst_bv_or": (_I, [_P, _P, _P, _U64, _P]),
+    "bst_bv_andnot": (_I, [_P, _P, _P, _U64, _P]),
+    "bst_bv_not": (_I, [_P, _P, _U64, _P]),
     "bst_bv_popcount": (_I, [_P, _U64, _P, _P]),
     "bst_profile_literals": (_I, [_P, _I, _I, _P, _P]),
     "bst_auc": (_I, [_P, _P, _I, _P]),
@@ -268,6 +270,14 @@ def bst_bv_and(a, b, out, n_rows, stream):
 
 def bst_bv_or(a, b, out, n_rows, stream):
     _call("bst_bv_or", _ptr(a), _ptr(b), _ptr(out), n_rows, stream)
+
+
+def bst_bv_andnot(a, b, out, n_rows, stream):
+    _call("bst_bv_andnot", _ptr(a), _ptr(b), _ptr(out), n_rows, stream)
+
+
+def bst_bv_not(a, out, n_rows, stream):
+    _call("bst_bv_not", _ptr(a), _ptr(out), n_rows, stream)
 
 
 def bst_bv_popcount(bv, n_rows, dev_count, stream):

@@ -216,6 +216,18 @@ def bv_or(a, b, n_rows, out=None, stream=None):
     return out
 
 
+def bv_andnot(a, b, n_rows, out=None, stream=None):
+    out = torch.empty_like(a) if out is None else out
+    L.bst_bv_andnot(a, b, out, n_rows, stream_handle(stream))
+    return out
+
+
+def bv_not(a, n_rows, out=None, stream=None):
+    out = torch.empty_like(a) if out is None else out
+    L.bst_bv_not(a, out, n_rows, stream_handle(stream))
+    return out
+
+
 def bv_popcount(bv, n_rows, stream=None) -> torch.Tensor:
     count = torch.zeros(1, dtype=torch.int64, device=bv.device)
     L.bst_bv_popcount(bv, n_rows, count, stream_handle(stream))

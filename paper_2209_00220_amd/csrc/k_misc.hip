@@ -27,7 +27,8 @@ __global__ __launch_bounds__(kBlock) void k_bv_binop(const uint64_t* __restrict_
                                                      uint64_t* __restrict__ out, uint64_t n, int op) {
     const uint64_t nwords = (n + 63) >> 6;
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t v = op == 0 ? (a[w] & b[w]) : (a[w] | b[w]);
+        // 0: a AND b, 1: a OR b, 2: a AND NOT b, 3: NOT a (b unused)
+        uint64_t v = op == 0 ? (a[w] & b[w]) : op == 1 ? (a[w] | b[w]) : op == 2 ? (a[w] & ~b[w]) : ~a[w];
         out[w] = v & valid_mask(w, n);
     }
 }
@@ -416,6 +417,22 @@ int bst_bv_or(const uint64_t* a, const uint64_t* b, uint64_t* out, uint64_t n_ro
     hipLaunchKernelGGL(k_bv_binop, dim3(elem_grid((n_rows + 63) / 64)), dim3(kBlock), 0, (hipStream_t)stream, a, b, out,
                        n_rows, 1);
     return hip_check(hipGetLastError(), "bv_or launch");
+}
+
+int bst_bv_andnot(const uint64_t* a, const uint64_t* b, uint64_t* out, uint64_t n_rows, void* stream) {
+    if (n_rows == 0) return BST_OK;
+    if (!a || !b || !out) return set_error(BST_EINVAL, "NULL argument");
+    hipLaunchKernelGGL(k_bv_binop, dim3(elem_grid((n_rows + 63) / 64)), dim3(kBlock), 0, (hipStream_t)stream, a, b, out,
+                       n_rows, 2);
+    return hip_check(hipGetLastError(), "bv_andnot launch");
+}
+
+int bst_bv_not(const uint64_t* a, uint64_t* out, uint64_t n_rows, void* stream) {
+    if (n_rows == 0) return BST_OK;
+    if (!a || !out) return set_error(BST_EINVAL, "NULL argument");
+    hipLaunchKernelGGL(k_bv_binop, dim3(elem_grid((n_rows + 63) / 64)), dim3(kBlock), 0, (hipStream_t)stream, a, a, out,
+                       n_rows, 3);
+    return hip_check(hipGetLastError(), "bv_not launch");
 }
 
 int bst_bv_popcount(const uint64_t* bv, uint64_t n_rows, uint64_t* dev_count, void* stream) {

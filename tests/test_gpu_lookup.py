@@ -108,7 +108,7 @@ def test_compact_overflow_flag():
 
 
 def test_bitvector_helpers():
-    from paper_2209_00220_amd.column import bv_and, bv_from_numpy, bv_or, bv_popcount, bv_to_numpy
+    from paper_2209_00220_amd.column import bv_and, bv_andnot, bv_from_numpy, bv_not, bv_or, bv_popcount, bv_to_numpy
 
     n = 123_457
     a = datagen.random_mask_words(n, seed=1, density=0.3)
@@ -117,4 +117,26 @@ def test_bitvector_helpers():
     ra, rb = unpack_bits(a, n), unpack_bits(b, n)
     assert np.array_equal(bv_to_numpy(bv_and(ta, tb, n)), pack_bits(ra & rb))
     assert np.array_equal(bv_to_numpy(bv_or(ta, tb, n)), pack_bits(ra | rb))
+    assert np.array_equal(bv_to_numpy(bv_andnot(ta, tb, n)), pack_bits(ra & ~rb))
+    assert np.array_equal(bv_to_numpy(bv_not(ta, n)), pack_bits(~ra))
     assert int(bv_popcount(ta, n).item()) == int(ra.sum())
+
+
+def test_disjunction_and_negation_of_scans():
+    # (x < a OR x > b) AND NOT (x = c) on every layout, against the plain definition
+    from paper_2209_00220_amd.column import bv_andnot, bv_not, bv_or, bv_to_numpy
+
+    n, w = 77_777, 16
+    x = datagen.zipf_column(n, w, 1.2, seed=21)
+    a, b, c = int(np.quantile(x, 0.2)), int(np.quantile(x, 0.7)), int(x[5])
+    from oracle.scan import scan_values
+
+    want = (scan_values(x, "lt", a) | scan_values(x, "gt", b)) & ~scan_values(x, "eq", c)
+    cols = device_columns(x, w)
+    try:
+        for lay, (_, dc) in cols.items():
+            r = bv_andnot(bv_or(dc.scan("lt", a), dc.scan("gt", b), n), dc.scan("eq", c), n)
+            assert np.array_equal(bv_to_numpy(r), pack_bits(want)), lay
+            assert np.array_equal(bv_to_numpy(bv_not(r, n)), pack_bits(~want)), lay
+    finally:
+        close_columns(cols)
