@@ -54,7 +54,16 @@ extern "C" {
 #define BST_DEV_OVERFLOW 2u /* more selected rows than the output capacity        */
 
 /* ---- layouts, operators, limits --------------------------------------- */
-typedef enum { BST_BITPACKED = 0, BST_BYTESLICE = 1, BST_PPVBS = 2 } bst_layout;
+typedef enum {
+    BST_BITPACKED = 0,
+    BST_BYTESLICE = 1,
+    BST_PPVBS = 2,
+    /* PP-VBS over the categorical PPE of Algorithm 2 (Sec. 3.1): codes follow
+     * descending frequency, not value order, so only '=' and '!=' scans apply
+     * (other operators return BST_EINVAL).  Accepted by the encode calls; the
+     * column then reports layout BST_PPVBS with categorical = 1. */
+    BST_PPVBS_CATEGORICAL = 3
+} bst_layout;
 
 /* Sec. 2.2: scans take =, !=, >, <, <=, >= and BETWEEN (lo <= v <= hi). */
 typedef enum {
@@ -94,7 +103,7 @@ typedef struct {
     uint32_t k_max;       /* bytes of the longest code (slices used)               */
     uint32_t dir_stride;  /* rows per PP-VBS directory entry                       */
     uint32_t domain_mode; /* 1: code = value; 0: code = dictionary rank / PPE code */
-    uint32_t reserved;
+    uint32_t categorical; /* 1: PP-VBS codes from Algorithm 2 (= and != only)        */
     uint64_t n_rows;
     uint64_t n_distinct;
     uint64_t bytes[BST_NBUF];          /* device bytes each slot needs (0 = unused) */

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libbytestore.so")
 BST_OK = 0
 BST_DEV_BAD_ROW = 1
 BST_DEV_OVERFLOW = 2
-BITPACKED, BYTESLICE, PPVBS = 0, 1, 2
+BITPACKED, BYTESLICE, PPVBS, PPVBS_CATEGORICAL = 0, 1, 2, 3
 LAYOUT_NAMES = {BITPACKED: "bitpacked", BYTESLICE: "byteslice", PPVBS: "ppvbs"}
 LT, LE, GT, GE, EQ, NE, BETWEEN = range(7)
 OP_CODES = {"lt": LT, "le": LE, "gt": GT, "ge": GE, "eq": EQ, "ne": NE, "between": BETWEEN}
@@ -41,7 +41,7 @@ class Pred(ctypes.Structure):
 class ColumnInfo(ctypes.Structure):
     _fields_ = [
         ("layout", ctypes.c_uint32), ("width_bits", ctypes.c_uint32), ("k_max", ctypes.c_uint32),
-        ("dir_stride", ctypes.c_uint32), ("domain_mode", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("dir_stride", ctypes.c_uint32), ("domain_mode", ctypes.c_uint32), ("categorical", ctypes.c_uint32),
         ("n_rows", ctypes.c_uint64), ("n_distinct", ctypes.c_uint64),
         ("bytes", ctypes.c_uint64 * NBUF), ("total_bytes", ctypes.c_uint64),
         ("rows_by_len", ctypes.c_uint64 * (KMAX + 1)), ("layout_bytes", ctypes.c_uint64),

@@ -12,7 +12,8 @@ import torch
 
 from . import _lib as L
 
-LAYOUTS = {"bitpacked": L.BITPACKED, "byteslice": L.BYTESLICE, "ppvbs": L.PPVBS}
+LAYOUTS = {"bitpacked": L.BITPACKED, "byteslice": L.BYTESLICE, "ppvbs": L.PPVBS,
+           "ppvbs_categorical": L.PPVBS_CATEGORICAL}
 
 
 def layout_code(layout) -> int:

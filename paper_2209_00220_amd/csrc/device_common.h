@@ -721,6 +721,17 @@ __device__ __forceinline__ uint32_t trie_rank(const DevCol& c, uint64_t code, ui
     }
 }
 
+// Frequency rank of a categorical code (Algorithm 2's fill order inverted):
+// levels below B are full, 255 * 256^(b-1) codes each, filled pointer-major;
+// level B is filled slot-major.
+__device__ __forceinline__ uint64_t categorical_rank(uint64_t code, uint32_t len, uint32_t B) {
+    uint64_t base = 0;
+    for (uint32_t b = 1; b < len; ++b) base += 255ull << (8 * (b - 1));
+    const uint64_t slot = code & 0xffu, path = code >> 8;
+    if (len < B) return base + path * 255 + (slot - 1);
+    return base + (slot - 1) * (1ull << (8 * (B - 1))) + path;
+}
+
 __device__ __forceinline__ uint32_t lookup_row(const DevCol& c, uint64_t r) {
     const uint64_t pos1 = (r & ~(uint64_t)(kTileRows - 1)) + ((r & 63) << 5) + ((r >> 6) & 31);
     if (c.layout == BST_PPVBS) {
@@ -735,6 +746,7 @@ __device__ __forceinline__ uint32_t lookup_row(const DevCol& c, uint64_t r) {
             code = (code << 8) | c.bs[j][off];
             len = j;
         }
+        if (c.categorical) return c.dict[categorical_rank(code, len, c.K)];
         return c.dict[trie_rank(c, code, len)];
     }
     if (c.layout == BST_BYTESLICE) {

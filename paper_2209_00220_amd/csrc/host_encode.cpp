@@ -360,9 +360,49 @@ void choose_staging(const HostColumn& c, ScanLit* s, int pct) {
     s->stage = (pct <= 0 || pct > 100) ? 33u : std::max<uint32_t>(1u, (uint32_t)((32 * pct + 99) / 100));
 }
 
+// Categorical PPE (Sec. 3.1, Algorithm 2): the distinct values, taken in
+// descending frequency (ties: smaller value first), fill a balanced 256-way tree
+// breadth first.  Level b holds the codes (c << 8) + i for every pointer path c
+// of b - 1 bytes and slot i = 1..255; every level but the last is full, and the
+// last level is filled slot by slot (i outer, c inner) so its values spread over
+// all of its nodes.  code/clen are indexed by sorted dictionary position;
+// by_code[alpha] = dictionary position of the alpha-th most frequent value.
+static int categorical_codes(const std::vector<uint64_t>& Q, std::vector<uint64_t>& code, std::vector<uint8_t>& clen,
+                             uint32_t* K, std::vector<uint32_t>& by_code) {
+    const uint64_t n = Q.size();
+    code.assign(n, 0);
+    clen.assign(n, 0);
+    by_code.resize(n);
+    std::iota(by_code.begin(), by_code.end(), 0u);
+    std::stable_sort(by_code.begin(), by_code.end(), [&](uint32_t a, uint32_t b) { return Q[a] > Q[b]; });
+    uint32_t B = 0;   // levels: smallest B with 256^B >= n + 1
+    for (unsigned __int128 cap = 1; cap < (unsigned __int128)n + 1; cap *= 256) ++B;
+    if (B == 0) B = 1;
+    if (B > BST_KMAX) return set_error(BST_ERANGE, "code longer than BST_KMAX bytes");
+    uint64_t alpha = 0;
+    for (uint32_t b = 1; b < B && alpha < n; ++b) {
+        const uint64_t paths = 1ull << (8 * (b - 1));
+        for (uint64_t p = 0; p < paths && alpha < n; ++p)
+            for (uint32_t i = 1; i < 256 && alpha < n; ++i, ++alpha) {
+                code[by_code[alpha]] = (p << 8) + i;
+                clen[by_code[alpha]] = (uint8_t)b;
+            }
+    }
+    const uint64_t paths = 1ull << (8 * (B - 1));
+    for (uint32_t i = 1; i < 256 && alpha < n; ++i)
+        for (uint64_t p = 0; p < paths && alpha < n; ++p, ++alpha) {
+            code[by_code[alpha]] = (p << 8) + i;
+            clen[by_code[alpha]] = (uint8_t)B;
+        }
+    *K = B;
+    return BST_OK;
+}
+
 static int encode_column(const Dict& d, int layout, uint32_t width, uint32_t dir_stride, uint32_t T,
                          HostColumn& c) {
-    if (layout < BST_BITPACKED || layout > BST_PPVBS) return set_error(BST_EINVAL, "bad layout");
+    if (layout < BST_BITPACKED || layout > BST_PPVBS_CATEGORICAL) return set_error(BST_EINVAL, "bad layout");
+    const bool categorical = layout == BST_PPVBS_CATEGORICAL;
+    if (categorical) layout = BST_PPVBS;
     if (dir_stride == 0) dir_stride = kDefaultDirStride;
     if (log2_exact(dir_stride) < 6 || dir_stride > kTileRows)
         return set_error(BST_EINVAL, "dir_stride must be a power of two in [64, 2048]");
@@ -374,6 +414,22 @@ static int encode_column(const Dict& d, int layout, uint32_t width, uint32_t dir
     c.ntiles = (c.n + kTileRows - 1) / kTileRows;
     c.dir_stride = dir_stride;
     T = host_threads(T);
+    if (layout == BST_PPVBS && categorical) {
+        c.domain_mode = 0;
+        c.categorical = 1;
+        c.dict = d.A;
+        uint32_t K = 1;
+        std::vector<uint32_t> by_code;   // values in code (frequency) order
+        int rc = categorical_codes(d.Q, c.code, c.clen, &K, by_code);
+        if (rc) return rc;
+        for (uint32_t k = 0; k < c.nd; ++k) by_code[k] = d.A[by_code[k]];
+        c.K = K;
+        c.width = 8 * K;
+        c.buf[BST_BUF_DICT].resize(c.nd * 4);
+        if (c.nd) memcpy(c.buf[BST_BUF_DICT].data(), by_code.data(), c.nd * 4);
+        build_vbs(c, d.rank.data(), T);
+        return BST_OK;
+    }
     if (layout == BST_PPVBS) {
         c.domain_mode = 0;
         c.dict = d.A;
@@ -450,6 +506,8 @@ static void padded_code(const HostColumn& c, uint64_t k, uint64_t* code6, uint32
 
 int rewrite_predicate(const HostColumn& c, const bst_pred& p, ScanLit* out) {
     if (p.op < BST_LT || p.op > BST_BETWEEN) return set_error(BST_EINVAL, "bad predicate op");
+    if (c.categorical && p.op != BST_EQ && p.op != BST_NE)
+        return set_error(BST_EINVAL, "a categorical column supports '=' and '!=' scans only");
     // code space: dictionary entries 0..count-1 (domain mode: every w-bit value)
     const bool dom = (c.layout != BST_PPVBS) && c.domain_mode;
     const uint64_t count = dom ? (1ull << c.width) : c.nd;
@@ -687,6 +745,7 @@ int bst_host_info(const bst_host_column* hc, bst_column_info* info) {
     info->k_max = c.K;
     info->dir_stride = c.dir_stride;
     info->domain_mode = c.domain_mode;
+    info->categorical = c.categorical;
     info->n_rows = c.n;
     info->n_distinct = c.nd;
     for (int s = 0; s < BST_NBUF; ++s) {

@@ -28,6 +28,7 @@ struct Dict {
 
 struct HostColumn {
     uint32_t layout = 0, width = 0, K = 1, dir_stride = kDefaultDirStride, domain_mode = 0;
+    uint32_t categorical = 0;        // PP-VBS codes from Algorithm 2; dict then in code order
     uint64_t n = 0, nd = 0, ntiles = 0;
     bool codes_only = false;
     std::vector<uint32_t> dict;      // sorted distinct values (dictionary mode, PP-VBS)
@@ -73,6 +74,7 @@ int code_literal(const HostColumn& c, int op, uint64_t lo, uint32_t llo, uint64_
 struct DevCol {
     uint32_t layout, width, K, dir_shift;
     uint32_t domain_mode, trie_root;
+    uint32_t categorical, pad0;          // Algorithm 2 codes: decode arithmetically, dict by frequency
     uint64_t n, ntiles;
     const uint8_t* bs[BST_KMAX + 1];     // bs[1..K]
     const uint64_t* m[BST_KMAX + 1];     // m[2..K]

@@ -143,3 +143,38 @@ def test_auc_and_choose_match_oracle(L):
         layouts = [L.BITPACKED, L.BYTESLICE, L.PPVBS]
         want = oadv.choose(dict(zip(layouts, aucs)))
         assert layouts[L.bst_choose(layouts, aucs)] == want
+
+
+@pytest.mark.parametrize("name,x", [c for c in _columns() if c[0] != "zipf32"], ids=[c[0] for c in _columns() if c[0] != "zipf32"])
+def test_categorical_codes(L, name, x):
+    # Algorithm 2: codes in descending-frequency order (ties: smaller value), bit-exact
+    from oracle.ppe import ppe_categorical
+
+    A, Q, rank = build_dictionary(x)
+    order = np.argsort(-Q, kind="stable")
+    C, Lc = ppe_categorical(A.shape[0])
+    want_c = np.empty_like(C)
+    want_l = np.empty_like(Lc)
+    want_c[order] = C
+    want_l[order] = Lc
+    d = L.bst_dict_build(x)
+    try:
+        h = L.bst_encode(d, L.PPVBS_CATEGORICAL, 0, 0, 0)
+        try:
+            info = L.bst_host_info(h)
+            assert info.layout == L.PPVBS and info.categorical == 1
+            codes, lens = L.bst_host_code_table(h, A.shape[0])
+            assert np.array_equal(codes, want_c)
+            assert np.array_equal(lens.astype(np.int64), want_l)
+            K = int(want_l.max())
+            assert info.k_max == K
+            BS, M = vbs_build(want_c[rank], want_l[rank], K)
+            for j in range(1, K + 1):
+                assert np.array_equal(L.bst_host_paper_view(h, 0, j), BS[j]), j
+            for j in range(2, K + 1):
+                assert np.array_equal(L.bst_host_paper_view(h, 1, j).view(np.uint64), pack_bits(M[j])), j
+        finally:
+            L.bst_free_host(h)
+    finally:
+        L.bst_dict_free(d)
+
