@@ -140,3 +140,46 @@ def test_disjunction_and_negation_of_scans():
             assert np.array_equal(bv_to_numpy(bv_not(r, n)), pack_bits(~want)), lay
     finally:
         close_columns(cols)
+
+
+def test_empty_column_every_entry_point():
+    # n = 0: every call succeeds and produces nothing (tail rules with no rows)
+    from paper_2209_00220_amd.batch import Batch
+    from paper_2209_00220_amd.column import (DeviceColumn, Dictionary, HostColumn, bv_compact, bv_popcount,
+                                             u32_from_numpy)
+
+    x0 = np.zeros(0, dtype=np.uint32)
+    x1 = datagen.zipf_column(5000, 12, 1.0, seed=3)
+    d0, d1 = Dictionary(x0), Dictionary(x1)
+    keep = []
+    try:
+        for lay in ("ppvbs", "byteslice", "bitpacked", "ppvbs_categorical"):
+            w = 0 if lay.startswith("ppvbs") else 12
+            h0, h1 = HostColumn.encode(d0, lay, width=w), HostColumn.encode(d1, lay, width=w)
+            c0, c1 = DeviceColumn(h0), DeviceColumn(h1)
+            keep += [h0, h1, c0, c1]
+            op = "eq" if lay == "ppvbs_categorical" else "lt"
+            bv = c0.scan(op, 7)
+            assert bv.numel() == 0
+            _, ctr = c0.scan_stats(op, 7)
+            assert int(ctr.sum().item()) == 0
+            assert c0.lookup(u32_from_numpy(np.zeros(0, dtype=np.uint32))).numel() == 0
+            ids, count = bv_compact(bv, 0, 4)
+            assert int(count.item()) == 0 and int(bv_popcount(bv, 0).item()) == 0
+            vals, count = c0.lookup_bv(bv, 4)
+            assert int(count.item()) == 0
+            # a batch mixing the empty column with a real one
+            o0, o1 = c0.new_bv(), c1.new_bv()
+            b = Batch([(c0, op, 7, None, None), (c1, op, int(x1[0]), None, None)], [o0, o1])
+            b.launch()
+            torch.cuda.synchronize()
+            from paper_2209_00220_amd.column import bv_to_numpy
+            from oracle.scan import scan_values
+
+            assert np.array_equal(bv_to_numpy(o1), pack_bits(scan_values(x1, op, int(x1[0]))))
+            b.close()
+    finally:
+        for o in reversed(keep):
+            o.close()
+        d0.close()
+        d1.close()
