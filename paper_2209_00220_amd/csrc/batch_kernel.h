@@ -14,7 +14,7 @@ template <int MODE, int SHORT, bool DENSE, bool HAS_IN>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMinWaves, 8))) void k_batch_slices(
     const BatchHeader* __restrict__ hdr, const BatchItem* __restrict__ items, unsigned long long* __restrict__ counter,
     uint32_t grab) {
-    __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerBlock][kStageBytes];
+    __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerBlock][kWaveLds];
     uint8_t* lds = stage[threadIdx.x >> 6];
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t total = hdr->total_tiles;

@@ -267,6 +267,17 @@ __device__ __forceinline__ uint32_t group_mask(uint32_t v) {
 
 constexpr uint32_t kStageBytes = 2080;   // 130 chunks of 16 bytes: a 2048-byte run plus alignment
 
+// Per-wave LDS scratch of the row-sparse level (after the staged run): the list
+// of pending rows, then per lane dword of the tile the rows found in the
+// relation, the rows still tied with the lower / upper literal, and (for the
+// instrumented build) the rows equal on the level's byte.
+constexpr uint32_t kSparseRows = 64;
+struct SparseLds {
+    uint16_t list[kSparseRows];
+    uint32_t hit[64], lo[64], hi[64], eq[64];
+};
+constexpr uint32_t kWaveLds = kStageBytes + sizeof(SparseLds);
+
 // Copy bytes [start, start+len) of a slice into this wave's LDS buffer with
 // 16-byte loads from the aligned-down start; returns start's offset in the buffer.
 __device__ __forceinline__ uint32_t stage_run(const uint8_t* __restrict__ src, uint64_t start, uint32_t len,
@@ -289,6 +300,91 @@ __device__ __forceinline__ uint32_t stage_run(const uint8_t* __restrict__ src, u
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     return (uint32_t)(start - a);
+}
+
+// One level for a tile with at most 64 pending rows: one row per lane.  The
+// pending rows (bits of plov | phiv) are listed in LDS; each lane takes one,
+// finds its byte j (PP-VBS: the directory entry plus the M_j popcounts before
+// it; ByteSlice: its place in the tile-interleaved slice), gathers it, applies
+// the byte and length rules of the level to that row alone, and sets the row's
+// bits in the per-dword outcome arrays with LDS atomics; every lane then reads
+// back its dword.  incl: inclusive lane prefix of the M_j dword popcounts
+// (PP-VBS); row_excl / total: this lane's exclusive prefix and the tile's total
+// of pending rows.
+template <int MODE, bool DENSE, bool COUNT>
+__device__ __forceinline__ void sparse_level(const DevCol& c, const ScanLit& lit, uint64_t t, uint32_t j,
+                                             uint64_t run0, uint32_t cur_mv, uint32_t next_mv, uint32_t incl,
+                                             uint32_t& outv, uint32_t& plov, uint32_t& phiv, uint32_t lane,
+                                             SparseLds* sp, uint32_t row_excl, uint32_t total, uint32_t& eq_rows) {
+    const uint32_t K = c.K;
+    sp->hit[lane] = 0;
+    sp->lo[lane] = 0;
+    sp->hi[lane] = 0;
+    if (COUNT) sp->eq[lane] = 0;
+    uint32_t v = plov | phiv;
+    uint32_t idx = row_excl;
+    while (v) {
+        const uint32_t b = __builtin_ctz(v);
+        v &= v - 1;
+        sp->list[idx++] = (uint16_t)((lane << 5) | b);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // every lane runs the cross-lane reads (lanes past `total` on entry 0)
+    const uint32_t e = lane < total ? (uint32_t)sp->list[lane] : 0u;
+    const uint32_t jd = e >> 5, bit = e & 31, k = jd >> 1;
+    const uint32_t below = (1u << bit) - 1u;
+    const uint32_t plo_w = __shfl(plov, (int)jd, 64), phi_w = __shfl(phiv, (int)jd, 64);
+    const uint32_t nxt_w = __shfl(next_mv, (int)jd, 64);
+    uint32_t pos;
+    if (DENSE) {
+        pos = (((jd & 1) << 5) | bit) * 32 + k;   // tile-interleaved: lane-in-group * 32 + group
+    } else {
+        const uint32_t mlo = __shfl(cur_mv, (int)(2 * k), 64);
+        const uint32_t mhi = __shfl(cur_mv, (int)(2 * k + 1), 64);
+        const uint32_t before = __shfl(incl, (int)(k ? 2 * k - 1 : 0), 64);
+        pos = (k ? before : 0u) + ((jd & 1) ? (uint32_t)__builtin_popcount(mlo) : 0u) +
+              (uint32_t)__builtin_popcount(((jd & 1) ? mhi : mlo) & below);
+    }
+    if (lane < total) {
+        const uint32_t b = c.bs[j][run0 + pos];
+        const uint32_t cl = lit_byte(lit.lo, j), ch = lit_byte(lit.hi, j);
+        const bool plo = (plo_w >> bit) & 1, phi = (phi_w >> bit) & 1;
+        const bool more = j < K && (DENSE || ((nxt_w >> bit) & 1));   // the row has a byte j+1
+        const bool lo_open = j < lit.llo, hi_open = j < lit.lhi;      // the literal goes on after byte j
+        bool hit = false, keep_lo = false, keep_hi = false, eqb = false;
+        if (plo) {
+            eqb = b == cl;
+            if (MODE == kModeLT || MODE == kModeBetween) {
+                if (b < cl) hit = true;                                  // below
+                else if (b == cl && lo_open) { if (more) keep_lo = true; else hit = true; }   // prefix: below
+            } else if (MODE == kModeGT) {
+                if (b > cl) hit = true;                                  // above
+                else if (b == cl) { if (lo_open) keep_lo = more; else hit = more; }   // equal, then more: above
+            } else {
+                if (b == cl) { if (lo_open) keep_lo = more; else hit = !more; }       // equal over the literal
+            }
+        }
+        if (MODE == kModeBetween && phi) {
+            eqb = eqb || b == ch;
+            if (b > ch) hit = true;                                      // above the upper literal
+            else if (b == ch) { if (hi_open) keep_hi = more; else hit = hit || more; }
+        }
+        const uint32_t m = 1u << bit;
+        if (hit) atomicOr(&sp->hit[jd], m);
+        if (keep_lo) atomicOr(&sp->lo[jd], m);
+        if (keep_hi) atomicOr(&sp->hi[jd], m);
+        if (COUNT && eqb) atomicOr(&sp->eq[jd], m);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t h = sp->hit[lane];
+    outv = MODE == kModeBetween ? (outv & ~h) : (outv | h);
+    plov = sp->lo[lane];
+    phiv = MODE == kModeBetween ? sp->hi[lane] : 0u;
+    eq_rows = COUNT ? sp->eq[lane] : 0u;
 }
 
 // The length rule of a level on lane-held words (32 rows per lane dword): rows
@@ -444,6 +540,26 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
             incl = wave_incl_sum(__builtin_popcount(cur_mv), lane);
             run0 = c.dir[j][(t * kTileRows) >> c.dir_shift];
             runlen = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        }
+        // few pending rows: one row per lane
+        {
+            const uint32_t prow = __builtin_popcount(plov | phiv);
+            const uint32_t rincl = wave_incl_sum(prow, lane);
+            const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)rincl, 63);
+            if (total <= kSparseRows) {
+                if (COUNT) {
+                    st.rowbytes += total;
+                    st.alg += wave_sum(((pend >> (lane >> 1)) & 1) ? __builtin_popcount(cur_mv) : 0u, lane);
+                }
+                uint32_t eq_rows = 0;
+                sparse_level<MODE, false, COUNT>(c, lit, t, j, run0, cur_mv, next_mv, incl, outv, plov, phiv, lane,
+                                                 reinterpret_cast<SparseLds*>(lds + kStageBytes), rincl - prow, total,
+                                                 eq_rows);
+                if (COUNT && j < K) st.alg += 8ull * __builtin_popcount(group_mask(eq_rows));
+                pend = group_mask(plov | phiv);
+                cur_mv = next_mv;
+                continue;
+            }
         }
         // stage the tile's run of BS_j when enough groups need it
         const bool staged = (uint32_t)__builtin_popcount(pend) >= lit.stage;

@@ -11,7 +11,7 @@ template <int MODE, int SHORT, bool DENSE, bool HAS_IN, bool COUNT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMinWaves, 8))) void k_scan_slices(
     const DevCol c, const ScanLit lit, const uint64_t* __restrict__ in_mask, uint64_t* __restrict__ out,
     unsigned long long* __restrict__ counters) {
-    __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerBlock][kStageBytes];
+    __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerBlock][kWaveLds];
     uint8_t* lds = stage[threadIdx.x >> 6];
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t wave = uniform(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
