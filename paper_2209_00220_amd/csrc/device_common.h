@@ -495,6 +495,20 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
                 st.alg += 64ull * __builtin_popcount(pend);
                 st.rowbytes += wave_sum(__builtin_popcount(plov | phiv), lane);
             }
+            {
+                // few pending rows: gather just their bytes, one row per lane
+                const uint32_t prow = __builtin_popcount(plov | phiv);
+                const uint32_t rincl = wave_incl_sum(prow, lane);
+                const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)rincl, 63);
+                if (total <= kSparseRows) {
+                    uint32_t eq_rows = 0;
+                    sparse_level<MODE, true, COUNT>(c, lit, t, j, t * kTileRows, 0u, 0u, 0u, outv, plov, phiv, lane,
+                                                    reinterpret_cast<SparseLds*>(lds + kStageBytes), rincl - prow,
+                                                    total, eq_rows);
+                    pend = group_mask(plov | phiv);
+                    continue;
+                }
+            }
             const auto rj = buffer_rsrc(c.bs[j] + t * kTileRows, kTileRows);
             const uint4 a0 = buffer_load16(rj, lane * 32), a1 = buffer_load16(rj, lane * 32 + 16);
             const uint32_t bw[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
