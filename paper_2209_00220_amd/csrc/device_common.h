@@ -271,7 +271,7 @@ constexpr uint32_t kStageBytes = 2080;   // 130 chunks of 16 bytes: a 2048-byte 
 // of pending rows, then per lane dword of the tile the rows found in the
 // relation, the rows still tied with the lower / upper literal, and (for the
 // instrumented build) the rows equal on the level's byte.
-constexpr uint32_t kSparseRows = 64;
+constexpr uint32_t kSparseRows = 256;   // up to four rows per lane, in rounds of 64
 struct SparseLds {
     uint16_t list[kSparseRows];
     uint32_t hit[64], lo[64], hi[64], eq[64];
@@ -302,8 +302,9 @@ __device__ __forceinline__ uint32_t stage_run(const uint8_t* __restrict__ src, u
     return (uint32_t)(start - a);
 }
 
-// One level for a tile with at most 64 pending rows: one row per lane.  The
-// pending rows (bits of plov | phiv) are listed in LDS; each lane takes one,
+// One level for a tile with at most kSparseRows pending rows: one row per lane
+// and round of 64.  The pending rows (bits of plov | phiv) are listed in LDS;
+// each lane takes one per round,
 // finds its byte j (PP-VBS: the directory entry plus the M_j popcounts before
 // it; ByteSlice: its place in the tile-interleaved slice), gathers it, applies
 // the byte and length rules of the level to that row alone, and sets the row's
@@ -331,51 +332,54 @@ __device__ __forceinline__ void sparse_level(const DevCol& c, const ScanLit& lit
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // every lane runs the cross-lane reads (lanes past `total` on entry 0)
-    const uint32_t e = lane < total ? (uint32_t)sp->list[lane] : 0u;
-    const uint32_t jd = e >> 5, bit = e & 31, k = jd >> 1;
-    const uint32_t below = (1u << bit) - 1u;
-    const uint32_t plo_w = __shfl(plov, (int)jd, 64), phi_w = __shfl(phiv, (int)jd, 64);
-    const uint32_t nxt_w = __shfl(next_mv, (int)jd, 64);
-    uint32_t pos;
-    if (DENSE) {
-        pos = (((jd & 1) << 5) | bit) * 32 + k;   // tile-interleaved: lane-in-group * 32 + group
-    } else {
-        const uint32_t mlo = __shfl(cur_mv, (int)(2 * k), 64);
-        const uint32_t mhi = __shfl(cur_mv, (int)(2 * k + 1), 64);
-        const uint32_t before = __shfl(incl, (int)(k ? 2 * k - 1 : 0), 64);
-        pos = (k ? before : 0u) + ((jd & 1) ? (uint32_t)__builtin_popcount(mlo) : 0u) +
-              (uint32_t)__builtin_popcount(((jd & 1) ? mhi : mlo) & below);
-    }
-    if (lane < total) {
-        const uint32_t b = c.bs[j][run0 + pos];
-        const uint32_t cl = lit_byte(lit.lo, j), ch = lit_byte(lit.hi, j);
-        const bool plo = (plo_w >> bit) & 1, phi = (phi_w >> bit) & 1;
-        const bool more = j < K && (DENSE || ((nxt_w >> bit) & 1));   // the row has a byte j+1
-        const bool lo_open = j < lit.llo, hi_open = j < lit.lhi;      // the literal goes on after byte j
-        bool hit = false, keep_lo = false, keep_hi = false, eqb = false;
-        if (plo) {
-            eqb = b == cl;
-            if (MODE == kModeLT || MODE == kModeBetween) {
-                if (b < cl) hit = true;                                  // below
-                else if (b == cl && lo_open) { if (more) keep_lo = true; else hit = true; }   // prefix: below
-            } else if (MODE == kModeGT) {
-                if (b > cl) hit = true;                                  // above
-                else if (b == cl) { if (lo_open) keep_lo = more; else hit = more; }   // equal, then more: above
-            } else {
-                if (b == cl) { if (lo_open) keep_lo = more; else hit = !more; }       // equal over the literal
+    for (uint32_t base = 0; base < total; base += 64) {
+        // every lane runs the cross-lane reads (lanes past `total` on entry 0)
+        const uint32_t ent = base + lane;
+        const uint32_t e = ent < total ? (uint32_t)sp->list[ent] : 0u;
+        const uint32_t jd = e >> 5, bit = e & 31, k = jd >> 1;
+        const uint32_t below = (1u << bit) - 1u;
+        const uint32_t plo_w = __shfl(plov, (int)jd, 64), phi_w = __shfl(phiv, (int)jd, 64);
+        const uint32_t nxt_w = __shfl(next_mv, (int)jd, 64);
+        uint32_t pos;
+        if (DENSE) {
+            pos = (((jd & 1) << 5) | bit) * 32 + k;   // tile-interleaved: lane-in-group * 32 + group
+        } else {
+            const uint32_t mlo = __shfl(cur_mv, (int)(2 * k), 64);
+            const uint32_t mhi = __shfl(cur_mv, (int)(2 * k + 1), 64);
+            const uint32_t before = __shfl(incl, (int)(k ? 2 * k - 1 : 0), 64);
+            pos = (k ? before : 0u) + ((jd & 1) ? (uint32_t)__builtin_popcount(mlo) : 0u) +
+                  (uint32_t)__builtin_popcount(((jd & 1) ? mhi : mlo) & below);
+        }
+        if (ent < total) {
+            const uint32_t b = c.bs[j][run0 + pos];
+            const uint32_t cl = lit_byte(lit.lo, j), ch = lit_byte(lit.hi, j);
+            const bool plo = (plo_w >> bit) & 1, phi = (phi_w >> bit) & 1;
+            const bool more = j < K && (DENSE || ((nxt_w >> bit) & 1));   // the row has a byte j+1
+            const bool lo_open = j < lit.llo, hi_open = j < lit.lhi;      // the literal goes on after byte j
+            bool hit = false, keep_lo = false, keep_hi = false, eqb = false;
+            if (plo) {
+                eqb = b == cl;
+                if (MODE == kModeLT || MODE == kModeBetween) {
+                    if (b < cl) hit = true;                                  // below
+                    else if (b == cl && lo_open) { if (more) keep_lo = true; else hit = true; }   // prefix: below
+                } else if (MODE == kModeGT) {
+                    if (b > cl) hit = true;                                  // above
+                    else if (b == cl) { if (lo_open) keep_lo = more; else hit = more; }   // equal, then more: above
+                } else {
+                    if (b == cl) { if (lo_open) keep_lo = more; else hit = !more; }       // equal over the literal
+                }
             }
+            if (MODE == kModeBetween && phi) {
+                eqb = eqb || b == ch;
+                if (b > ch) hit = true;                                      // above the upper literal
+                else if (b == ch) { if (hi_open) keep_hi = more; else hit = hit || more; }
+            }
+            const uint32_t m = 1u << bit;
+            if (hit) atomicOr(&sp->hit[jd], m);
+            if (keep_lo) atomicOr(&sp->lo[jd], m);
+            if (keep_hi) atomicOr(&sp->hi[jd], m);
+            if (COUNT && eqb) atomicOr(&sp->eq[jd], m);
         }
-        if (MODE == kModeBetween && phi) {
-            eqb = eqb || b == ch;
-            if (b > ch) hit = true;                                      // above the upper literal
-            else if (b == ch) { if (hi_open) keep_hi = more; else hit = hit || more; }
-        }
-        const uint32_t m = 1u << bit;
-        if (hit) atomicOr(&sp->hit[jd], m);
-        if (keep_lo) atomicOr(&sp->lo[jd], m);
-        if (keep_hi) atomicOr(&sp->hi[jd], m);
-        if (COUNT && eqb) atomicOr(&sp->eq[jd], m);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -496,11 +500,14 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
                 st.rowbytes += wave_sum(__builtin_popcount(plov | phiv), lane);
             }
             {
-                // few pending rows: gather just their bytes, one row per lane
+                // few pending rows: gather just their bytes, one row per lane and
+                // round (a single literal's byte compares on the whole 2 KB are
+                // cheap enough that more than one round does not pay)
+                constexpr uint32_t kMaxRows = MODE == kModeBetween ? kSparseRows : 64;
                 const uint32_t prow = __builtin_popcount(plov | phiv);
                 const uint32_t rincl = wave_incl_sum(prow, lane);
                 const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)rincl, 63);
-                if (total <= kSparseRows) {
+                if (total <= kMaxRows) {
                     uint32_t eq_rows = 0;
                     sparse_level<MODE, true, COUNT>(c, lit, t, j, t * kTileRows, 0u, 0u, 0u, outv, plov, phiv, lane,
                                                     reinterpret_cast<SparseLds*>(lds + kStageBytes), rincl - prow,
@@ -555,7 +562,7 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
             run0 = c.dir[j][(t * kTileRows) >> c.dir_shift];
             runlen = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
         }
-        // few pending rows: one row per lane
+        // few pending rows: one row per lane and round
         {
             const uint32_t prow = __builtin_popcount(plov | phiv);
             const uint32_t rincl = wave_incl_sum(prow, lane);
