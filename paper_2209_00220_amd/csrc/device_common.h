@@ -116,6 +116,7 @@ __device__ __forceinline__ uint64_t vbs_group_base(const DevCol& c, uint32_t j, 
 struct TileData {
     uint4 q0, q1;   // 32 first-slice bytes: byte k is row tile*2048 + 64k + lane
     uint32_t m2;    // PP-VBS: dword `lane` of the tile's 32 M_2 words (0 when unused)
+    uint32_t m3;    // PP-VBS: the same of M_3 (0 when the column has no third byte)
     uint32_t in;    // dword `lane` of the tile's 32 incoming-mask words (all ones when none)
 };
 
@@ -158,6 +159,7 @@ __device__ __forceinline__ TileData load_tile(const DevCol& c, const uint64_t* _
     d.q0 = buffer_load16(r1, lane * 32);
     d.q1 = buffer_load16(r1, lane * 32 + 16);
     d.m2 = DENSE ? 0u : load_mask_dword(c, 2, t, lane, valid);
+    d.m3 = DENSE ? 0u : load_mask_dword(c, 3, t, lane, valid);
     d.in = ~0u;
     if (HAS_IN) {
         // the mask has ceil(n/64) words; the last tile may hold fewer than 32
@@ -550,7 +552,7 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
     uint32_t cur_mv = DENSE ? 0u : td.m2;   // this lane's dword of the tile's M_j words
     for (uint32_t j = 2; pend != 0 && j <= K; ++j) {
         if (COUNT && j == 2) st.deep_groups += __builtin_popcount(pend);
-        const uint32_t next_mv = (!DENSE && j < K) ? load_mask_dword(c, j + 1, t, lane) : 0u;
+        const uint32_t next_mv = (!DENSE && j < K) ? (j == 2 ? td.m3 : load_mask_dword(c, j + 1, t, lane)) : 0u;
         uint32_t incl = 0;
         uint64_t run0;
         uint32_t runlen;
