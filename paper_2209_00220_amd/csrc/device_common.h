@@ -556,19 +556,22 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
         uint32_t incl = 0;
         uint64_t run0;
         uint32_t runlen;
+        // one lane prefix for two counts: this level's bytes (M_j bits, high half)
+        // and the pending rows (low half); each sums to at most 2048
+        const uint32_t prow = __builtin_popcount(plov | phiv);
+        const uint32_t both = wave_incl_sum(((uint32_t)__builtin_popcount(cur_mv) << 16) | prow, lane);
+        const uint32_t rincl = both & 0xffffu;
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)both, 63) & 0xffffu;
         if (DENSE) {
             run0 = t * kTileRows;
             runlen = kTileRows;
         } else {
-            incl = wave_incl_sum(__builtin_popcount(cur_mv), lane);
+            incl = both >> 16;
             run0 = c.dir[j][(t * kTileRows) >> c.dir_shift];
-            runlen = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+            runlen = (uint32_t)__builtin_amdgcn_readlane((int)both, 63) >> 16;
         }
         // few pending rows: one row per lane and round
         {
-            const uint32_t prow = __builtin_popcount(plov | phiv);
-            const uint32_t rincl = wave_incl_sum(prow, lane);
-            const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)rincl, 63);
             if (total <= kSparseRows) {
                 if (COUNT) {
                     st.rowbytes += total;
