@@ -104,13 +104,10 @@ __device__ __forceinline__ uint64_t vbs_group_base(const DevCol& c, uint32_t j, 
 // bytes are not all zero), and at j = l a row with a byte l+1 is greater, one
 // without it equal.  Bytes compare unsigned.
 //
-// Phase 1 compares byte 1 of all 32 groups (no memory wait, the tile is in
-// registers) and records the groups that still have pending rows.  Phase 2
-// settles only those groups: M_2 words come from the tile's prefetched mask
-// dwords, and the byte-2 gathers of up to four groups are issued before any of
-// them is waited on; deeper bytes, rarer still, are read group by group.  So
-// later slices are read only for groups whose rows are undecided -- the early
-// stop of Algorithm 3 at 64-row granularity, tested wave-uniformly.
+// Byte 1 is compared for all 32 groups from registers; the presence of byte 2
+// (M_2, prefetched with the tile) settles what the lengths decide; later bytes
+// are read only for rows still undecided -- the early stop of Algorithm 3,
+// tested wave-uniformly per tile and level (see process_tile).
 
 // Per-lane registers of one tile.
 struct TileData {

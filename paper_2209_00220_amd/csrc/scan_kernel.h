@@ -1,5 +1,5 @@
 // Single-column scans of the slice layouts (PP-VBS, ByteSlice): one wave per
-// 2048-row tile, grid-stride over tiles, two tiles' loads in flight.
+// 2048-row tile, grid-stride over tiles, the next two tiles' loads in flight.
 #pragma once
 
 #include "device_common.h"
