@@ -238,12 +238,18 @@ __device__ uint64_t full_read_bytes(const DevCol& c, const ScanLit& lit, uint64_
 }
 
 // Inclusive prefix sum over the wave's lanes.
+// DPP moves (row_shr within each 16-lane row, then row_bcast:15 / :31 across
+// rows) instead of LDS permutes: six dependent VALU adds.  Lanes without a
+// source lane, and rows masked off, add 0.
 __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v, uint32_t lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(v, o, 64);
-        if ((int)lane >= o) v += y;
-    }
+    (void)lane;
+    constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowShr + 1, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowShr + 2, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowShr + 4, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowShr + 8, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowBcast15, 0xa, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowBcast31, 0xc, 0xf, false);
     return v;
 }
 
