@@ -17,8 +17,10 @@ scan kernel (algorithmic bytes per launch over its HIP-event duration against
 CPU oracle timed on a bounded sample.
 
 Other workloads print their own line: ``--workload wide`` (16-column table:
-layout advisor per column, pipelined conjunction, lookups) and
-``--workload batch`` (256 predicates over 64 columns in one launch).
+layout advisor per column, pipelined conjunction, lookups),
+``--workload batch`` (256 predicates over 64 columns in one launch),
+``--workload serve`` (continuous batching over resident tables) and
+``--workload sweep`` (skew and domain sensitivity).
 """
 from __future__ import annotations
 
@@ -333,6 +335,82 @@ def batch_main(args):
     print(json.dumps(out), flush=True)
 
 
+def serve_main(args):
+    """Serving workload: tables of 4 resident PP-VBS columns (rows log-uniform in
+    [--serve-rows-lo, --serve-rows-hi], w in 8..32, Zipf s in [0.5, 1.5]);
+    queries of 1-4 predicates and a lookup of 1-2 columns.  Saturation
+    throughput and p50/p99 under Poisson arrivals at 25/50/80 % of the
+    one-query-at-a-time saturation, served with continuous batching and one
+    query at a time."""
+    import numpy as np
+    import torch
+
+    import datagen
+    from datagen import workloads
+    from paper_2209_00220_amd.column import DeviceColumn, Dictionary, HostColumn
+    from paper_2209_00220_amd.serve import GpuExecutor, Query, Server, latency_summary, poisson_arrivals, run_serial
+
+    torch.cuda.set_device(0)
+    spec = workloads.config5_tables(args.serve_tables, 4, args.serve_rows_lo, args.serve_rows_hi)
+    tables, counts, keep = {}, [], []
+    rows_total = 0
+    for t, (n, cols) in enumerate(spec):
+        tables["t%d" % t], cs = {}, []
+        for c, (w, sk, seed) in enumerate(cols):
+            x = datagen.zipf_column(n, w, sk, seed=seed)
+            cs.append(workloads.value_counts(x, w))
+            d = Dictionary(x)
+            hc = HostColumn.encode(d, "ppvbs")
+            d.close()
+            tables["t%d" % t]["c%d" % c] = DeviceColumn(hc)
+            keep.append(hc)
+            del x
+        counts.append(cs)
+        rows_total += 4 * n
+        progress("table %d / %d: %d rows x 4 columns" % (t + 1, len(spec), n))
+    resident = sum(int(dc.device_bytes) for cols in tables.values() for dc in cols.values())
+    raw = workloads.config5_queries(counts, args.serve_queries, seed=56)
+    qs = [Query(i, "t%d" % t, [("c%d" % c, op, lo, hi) for c, op, lo, hi in preds], ["c%d" % c for c in look])
+          for i, (t, preds, look) in enumerate(raw)]
+    ex = GpuExecutor(tables)
+    budget = int(args.serve_budget_gb * (1 << 30))
+    warm = [Query(10_000 + q.qid, q.table, q.preds, q.lookups) for q in qs[:16]]
+    Server(ex, budget).run(warm, keep_values=False)
+    run_serial(ex, warm, keep_values=False)
+    progress("saturation: all %d queries at once" % len(qs))
+    srv = Server(ex, budget)
+    served = srv.run(qs, keep_values=False)
+    serial = run_serial(ex, qs, keep_values=False)
+    for q in qs:   # the two schedules give every query the same rows
+        assert served[q.qid].count == serial[q.qid].count, q
+    sat, sat_serial = latency_summary(served), latency_summary(serial)
+    loads = []
+    for frac in (0.25, 0.5, 0.8):
+        qps = frac * sat_serial["qps"]
+        for q, a in zip(qs, poisson_arrivals(len(qs), qps, seed=57)):
+            q.arrival = float(a)
+        a = latency_summary(Server(ex, budget).run(qs, keep_values=False))
+        b = latency_summary(run_serial(ex, qs, keep_values=False))
+        loads.append({"offered_qps": round(qps, 1), "p50_ms": round(a["p50_ms"], 3), "p99_ms": round(a["p99_ms"], 3),
+                      "one_at_a_time_p50_ms": round(b["p50_ms"], 3), "one_at_a_time_p99_ms": round(b["p99_ms"], 3)})
+        progress("load %.0f%%: %s" % (100 * frac, json.dumps(loads[-1])))
+    out = {
+        "metric": "served queries/s at saturation (continuous batching vs one query at a time); p50/p99 under load",
+        "value": round(sat["qps"], 1), "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "%d tables x 4 PP-VBS columns, rows log-uniform in [%.0e, %.0e] per table, "
+                               "w in 8..32, Zipf s in [0.5, 1.5]; %d queries of 1-4 predicates "
+                               "(<, >=, BETWEEN; selectivity log-uniform 0.01-50%%) + lookup of 1-2 columns"
+                               % (len(spec), args.serve_rows_lo, args.serve_rows_hi, len(qs)),
+                   "rows_resident": rows_total, "resident_bytes": resident, "budget_bytes": budget},
+        "saturation_qps_one_at_a_time": round(sat_serial["qps"], 1),
+        "speedup": round(sat["qps"] / sat_serial["qps"], 3),
+        "mean_batch": round(sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)), 2),
+        "loads": loads,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def sweep_main(args):
     """Skew and domain sensitivity: per (Zipf s, width w) the bytes per row of each
     layout and its '<' (about 10 %) and '=' (most frequent value) scan rates."""
@@ -380,10 +458,14 @@ def sweep_main(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("scan", "wide", "batch", "sweep"), default="scan",
+    ap.add_argument("--workload", choices=("scan", "wide", "batch", "serve", "sweep"), default="scan",
                     help="scan: the one-column benchmark (default); wide: 16-column table with the advisor, "
                          "a conjunction and lookups; batch: 256 predicates over 64 columns in one launch; "
+                         "serve: continuous batching over resident tables; "
                          "sweep: skew x domain sensitivity of every layout")
+    ap.add_argument("--serve-tables", type=int, default=8)
+    ap.add_argument("--serve-rows-lo", type=float, default=1e6)
+    ap.add_argument("--serve-rows-hi", type=float, default=1e8)
     ap.add_argument("--sweep-rows", type=int, default=50_000_000)
     ap.add_argument("--wide-rows", type=int, default=100_000_000)
     ap.add_argument("--batch-cols", type=int, default=64)
@@ -406,7 +488,7 @@ def main():
         if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
             print("bench.py measures one GPU; run with --gpus 1", file=sys.stderr)
             sys.exit(2)
-        {"wide": wide_main, "batch": batch_main, "sweep": sweep_main}[args.workload](args)
+        {"wide": wide_main, "batch": batch_main, "serve": serve_main, "sweep": sweep_main}[args.workload](args)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -138,3 +138,45 @@ def config4_predicates(counts, n_preds: int = 256, seed: int = 5):
             lo, hi, got = lit_between(v, k, sel)
             out.append((c, op, lo, hi, got))
     return out
+
+
+def config5_tables(n_tables: int = 8, n_cols: int = 4, n_lo: float = 1e6, n_hi: float = 1e8, seed: int = 55):
+    """Tables for the serving workload: n_t log-uniform in [n_lo, n_hi] (every
+    column of a table has n_t rows), width w ~ U{8..32}, Zipf s ~ U[0.5, 1.5].
+    Returns [(n_t, [(w, s, seed), ...])]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(n_tables):
+        n = int(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        cols = [(int(rng.integers(8, 33)), float(rng.uniform(0.5, 1.5)), 500 + 10 * t + c) for c in range(n_cols)]
+        out.append((n, cols))
+    return out
+
+
+def config5_queries(counts, n_queries: int, seed: int):
+    """Serving queries: counts[t][c] = (values, counts) of column c of table t.
+    Each query: 1-4 predicates on one table (op in <, >=, BETWEEN; selectivity
+    log-uniform in [0.01 %, 50 %]), then a lookup of 1-2 of its columns.
+    Returns [(table, [(column, op, lo, hi)], [lookup columns])]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_queries):
+        t = int(rng.integers(0, len(counts)))
+        nc = len(counts[t])
+        preds = []
+        for _ in range(int(rng.integers(1, 5))):
+            c = int(rng.integers(0, nc))
+            v, k = counts[t][c]
+            sel = float(np.exp(rng.uniform(np.log(1e-4), np.log(0.5))))
+            kind = int(rng.integers(0, 3))
+            if kind == 0:
+                preds.append((c, "lt", lit_lt(v, k, sel)[0], None))
+            elif kind == 1:
+                preds.append((c, "ge", lit_lt(v, k, 1.0 - sel)[0], None))
+            else:
+                lo, hi, _ = lit_between(v, k, sel)
+                preds.append((c, "between", lo, hi))
+        look = sorted(int(j) for j in rng.choice(nc, size=int(rng.integers(1, 3)), replace=False))
+        out.append((t, preds, look))
+    return out
+

@@ -298,8 +298,10 @@ uint64_t bst_batch_workspace_bytes(int n_items);
  * Prepare scans item i: cols[i] with preds[i], optional in_masks[i] (NULL
  * entry or NULL array = none), writing outs[i].  Literals are rewritten on the
  * host and the work list (item, tile) is uploaded into `workspace` on the
- * first launch.  The arrays are copied; columns and device buffers must stay
- * alive while the batch is used.
+ * first launch, by an asynchronous copy from a pinned staging ring that the
+ * library allocates once (8 MiB) and keeps until the process ends; the launch
+ * does not wait for the stream.  The arrays are copied; columns, `workspace`
+ * and the device buffers must stay alive until the launched work has run.
  */
 int bst_batch_prepare(const bst_column* const* cols, const bst_pred* preds,
                       const uint64_t* const* in_masks, uint64_t* const* outs, int n_items,
@@ -307,10 +309,12 @@ int bst_batch_prepare(const bst_column* const* cols, const bst_pred* preds,
 /*
  * Run every scan of the batch: items are grouped by kernel variant (layout,
  * operator or code width, one-byte literal, incoming mask), and each group is
- * one persistent launch of `grid` workgroups (0 = tuned default) whose waves
- * take at least `tiles_per_grab` (0 = tuned default) consecutive 2048-row tiles
- * at a time from the group's queue -- more when the group is large, so that a
- * wave takes about four times per group.  With use_graph != 0 the launch
+ * one persistent launch of up to `grid` workgroups (0 = tuned default; never
+ * more waves than the group has tiles) whose waves take at least
+ * `tiles_per_grab` (0 = tuned default) consecutive 2048-row tiles at a time
+ * from the group's queue -- more when the group is large, so that a wave takes
+ * about four times per group; a group too small to give every wave
+ * `tiles_per_grab` tiles is spread evenly over its waves instead.  With use_graph != 0 the launch
  * sequence is captured once into a HIP graph and replayed on later calls with
  * the same grid and grab size.  Errors: BST_EINVAL for a NULL batch, BST_EHIP
  * for a failed launch or capture.

@@ -7,9 +7,28 @@
 namespace bst {
 namespace dev {
 
-// Waves take `grab` consecutive tiles of the group's concatenated tile list at a
-// time and scan them item by item (a grab may straddle items); the per-tile
-// work is the single-column scan's, inlined.
+// Tiles are handed out in takes of `grab` consecutive tiles of the group's
+// concatenated tile list.  A wave's first take is fixed by its index; later
+// takes come from the group's counter and lie past the region of first takes
+// (waves * grab tiles).  So a group that the first takes cover costs no atomic,
+// and a large one costs one atomic per later take: atomics on one address
+// serialise, and thousands of them would cost more than a small group's scan.
+__device__ __forceinline__ uint64_t batch_first_take(uint32_t grab) {
+    return (uint64_t)uniform(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6)) * grab;
+}
+
+__device__ __forceinline__ uint64_t batch_next_take(unsigned long long* counter, uint32_t grab, uint64_t total,
+                                                    uint32_t lane) {
+    const uint64_t fixed = (uint64_t)gridDim.x * kWavesPerBlock * grab;
+    if (fixed >= total) return total;
+    uint64_t s = 0;
+    if (lane == 0) s = atomicAdd(counter, (unsigned long long)grab);
+    s = ((uint64_t)uniform((uint32_t)(s >> 32)) << 32) | uniform((uint32_t)s);
+    return fixed + s;
+}
+
+// Waves scan their takes item by item (a take may straddle items); the
+// per-tile work is the single-column scan's, inlined.
 template <int MODE, int SHORT, bool DENSE, bool HAS_IN>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMinWaves, 8))) void k_batch_slices(
     const BatchHeader* __restrict__ hdr, const BatchItem* __restrict__ items, unsigned long long* __restrict__ counter,
@@ -20,11 +39,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMinWave
     const uint64_t total = hdr->total_tiles;
     const uint32_t n_items = hdr->n_items;
     Stats st;
-    for (;;) {
-        uint64_t start = 0;
-        if (lane == 0) start = atomicAdd(counter, (unsigned long long)grab);
-        start = ((uint64_t)uniform((uint32_t)(start >> 32)) << 32) | uniform((uint32_t)start);
-        if (start >= total) break;
+    for (uint64_t start = batch_first_take(grab); start < total;
+         start = batch_next_take(counter, grab, total, lane)) {
         const uint64_t stop = std::min<uint64_t>(total, start + grab);
         for (uint32_t cur = batch_find(items, n_items, start); cur < n_items && items[cur].tile0 < stop; ++cur) {
             const BatchItem& it = items[cur];

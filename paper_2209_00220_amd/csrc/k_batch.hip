@@ -1,4 +1,6 @@
 // Batched scans: many predicates over many columns in one persistent launch.
+#include <deque>
+#include <mutex>
 #include <vector>
 
 #include "batch_kernel.h"
@@ -44,6 +46,99 @@ static BatchKernel batch_kernel(uint32_t kind, bool has_in) {
 
 }  // namespace dev
 }  // namespace bst
+
+// Pinned staging for batch uploads, one ring per process, allocated on first
+// use and kept until the process ends.  A launch copies its header and work
+// list into the ring and enqueues a true asynchronous copy from there, so the
+// host never waits for the stream and can prepare the next batch while the
+// device runs this one.  A region is reused only after the event recorded
+// behind its copy has completed.
+namespace {
+
+constexpr size_t kRingBytes = 8u << 20;
+constexpr size_t kRingAlign = 256;
+
+struct UploadRing {
+    std::mutex mu;
+    char* host = nullptr;
+    bool failed = false;
+    size_t head = 0;
+    struct Span {
+        size_t begin, end;
+        hipEvent_t ev;
+    };
+    std::deque<Span> live;   // regions whose copies may still be in flight, in ring order
+    std::vector<hipEvent_t> spare;
+};
+
+UploadRing& ring() {
+    static UploadRing* r = new UploadRing;   // never destroyed: its memory lives until exit
+    return *r;
+}
+
+// Copy `len` bytes from `src` to device address `dst` on `st` through the ring.
+// Returns BST_EHIP (with the message set) on a HIP error; a batch larger than
+// the ring, or a ring that could not be allocated, goes through a synchronous
+// copy instead.
+int ring_upload(void* dst, const void* src, size_t len, hipStream_t st) {
+    UploadRing& r = ring();
+    std::lock_guard<std::mutex> lock(r.mu);
+    if (!r.host && !r.failed) {
+        if (hipHostMalloc((void**)&r.host, kRingBytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            r.host = nullptr;
+            r.failed = true;
+        }
+    }
+    const size_t need = (len + kRingAlign - 1) / kRingAlign * kRingAlign;
+    if (!r.host || need > kRingBytes) {
+        int rc = hip_check(hipMemcpyAsync(dst, src, len, hipMemcpyHostToDevice, st), "batch upload");
+        if (!rc) rc = hip_check(hipStreamSynchronize(st), "batch upload sync");
+        return rc;
+    }
+    size_t b = r.head;
+    if (b + need > kRingBytes) b = 0;
+    const size_t e = b + need;
+    // retire finished regions, and wait for any that the new region overlaps
+    while (!r.live.empty()) {
+        UploadRing::Span& o = r.live.front();
+        const bool overlaps = o.begin < e && b < o.end;
+        if (!overlaps && hipEventQuery(o.ev) != hipSuccess) break;
+        if (overlaps) {
+            int rc = hip_check(hipEventSynchronize(o.ev), "batch upload wait");
+            if (rc) return rc;
+        }
+        r.spare.push_back(o.ev);
+        r.live.pop_front();
+    }
+    for (const UploadRing::Span& o : r.live)   // a younger region still in the way
+        if (o.begin < e && b < o.end) {
+            int rc = hip_check(hipEventSynchronize(o.ev), "batch upload wait");
+            if (rc) return rc;
+        }
+    hipEvent_t ev;
+    if (!r.spare.empty()) {
+        ev = r.spare.back();
+        r.spare.pop_back();
+    } else {
+        int rc = hip_check(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "batch upload event");
+        if (rc) return rc;
+    }
+    memcpy(r.host + b, src, len);
+    int rc = hip_check(hipMemcpyAsync(dst, r.host + b, len, hipMemcpyHostToDevice, st), "batch upload");
+    if (!rc) rc = hip_check(hipEventRecord(ev, st), "batch upload event");
+    if (rc) {
+        // the copy may be queued: keep the region reserved until the device is idle
+        (void)hipDeviceSynchronize();
+        r.spare.push_back(ev);
+        return rc;
+    }
+    r.live.push_back({b, e, ev});
+    r.head = e;
+    return BST_OK;
+}
+
+}  // namespace
 
 struct BatchGroup {
     uint32_t kind;
@@ -153,16 +248,25 @@ static int batch_enqueue(bst_batch* b, uint32_t grid, uint32_t grab, hipStream_t
     }
     if (!b->groups.empty()) {
         hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(128), 0, st, ws, (int)b->groups.size());
-        const uint64_t waves = (uint64_t)grid * kWavesPerBlock;
         for (size_t g = 0; g < b->groups.size(); ++g) {
             const BatchGroup& gr = b->groups[g];
             char* h = ws + g * kBatchHeaderBytes;
-            // at least `grab` tiles per take, and no more than about four takes per
-            // wave: every take is an atomic on the group's one counter
-            const uint64_t fair = (gr.tiles + 4 * waves - 1) / (4 * waves);
-            const uint32_t take = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(grab, fair), 1u << 20);
-            hipLaunchKernelGGL(batch_kernel(gr.kind, gr.has_in), dim3(grid), dim3(kBlock), 0, st,
-                               (const BatchHeader*)h, items + gr.first, (unsigned long long*)(h + 32), take);
+            // no more waves than the group has tiles
+            const uint32_t grid_g = (uint32_t)std::max<uint64_t>(
+                1, std::min<uint64_t>(grid, (gr.tiles + kWavesPerBlock - 1) / kWavesPerBlock));
+            const uint64_t waves = (uint64_t)grid_g * kWavesPerBlock;
+            // A small group spreads over all its waves, one take each.  A large one
+            // takes at least `grab` tiles at a time and no more than about four
+            // takes per wave: every take is an atomic on the group's one counter.
+            uint64_t take;
+            if (gr.tiles <= (uint64_t)grab * waves)
+                take = std::max<uint64_t>(1, (gr.tiles + waves - 1) / waves);
+            else
+                take = std::max<uint64_t>(grab, (gr.tiles + 4 * waves - 1) / (4 * waves));
+            take = std::min<uint64_t>(take, 1u << 20);
+            hipLaunchKernelGGL(batch_kernel(gr.kind, gr.has_in), dim3(grid_g), dim3(kBlock), 0, st,
+                               (const BatchHeader*)h, items + gr.first, (unsigned long long*)(h + 32),
+                               (uint32_t)take);
         }
     }
     return hip_check(hipGetLastError(), "batch launch");
@@ -174,17 +278,15 @@ int bst_batch_launch(bst_batch* b, uint32_t grid, uint32_t tiles_per_grab, int u
     if (grid == 0) grid = g_tune[BST_TUNE_BATCH_GRID] > 0 ? (uint32_t)g_tune[BST_TUNE_BATCH_GRID] : (uint32_t)props().cus * 8;
     if (tiles_per_grab == 0) tiles_per_grab = g_tune[BST_TUNE_BATCH_GRAB] > 0 ? (uint32_t)g_tune[BST_TUNE_BATCH_GRAB] : 16;
     if (!b->uploaded) {
-        char* ws = (char*)b->ws;
-        std::vector<char> head((size_t)kBatchGroupsMax * kBatchHeaderBytes, 0);
+        // header block and work list as one image, one copy
+        const size_t head = (size_t)kBatchGroupsMax * kBatchHeaderBytes;
+        std::vector<char> img(head + b->items.size() * sizeof(BatchItem), 0);
         for (size_t g = 0; g < b->groups.size(); ++g) {
             BatchHeader h{b->groups[g].tiles, b->groups[g].count, 0};
-            memcpy(head.data() + g * kBatchHeaderBytes, &h, sizeof(h));
+            memcpy(img.data() + g * kBatchHeaderBytes, &h, sizeof(h));
         }
-        int rc = hip_check(hipMemcpyAsync(ws, head.data(), head.size(), hipMemcpyHostToDevice, st), "batch upload");
-        if (!rc && !b->items.empty())
-            rc = hip_check(hipMemcpyAsync(ws + head.size(), b->items.data(), b->items.size() * sizeof(BatchItem),
-                                          hipMemcpyHostToDevice, st), "batch upload");
-        if (!rc) rc = hip_check(hipStreamSynchronize(st), "batch upload sync");
+        if (!b->items.empty()) memcpy(img.data() + head, b->items.data(), b->items.size() * sizeof(BatchItem));
+        int rc = ring_upload(b->ws, img.data(), img.size(), st);
         if (rc) return rc;
         b->uploaded = true;
     }

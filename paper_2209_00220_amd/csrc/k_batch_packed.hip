@@ -1,6 +1,6 @@
 // Batched Bit-Packed scans: one persistent kernel per code width (own
 // translation unit, compiled alongside the slice-layout batch kernels).
-#include "device_common.h"
+#include "batch_kernel.h"
 
 namespace bst {
 namespace dev {
@@ -13,11 +13,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_packed(const BatchHeader* __re
     const uint64_t total = hdr->total_tiles;
     const uint32_t n_items = hdr->n_items;
     uint64_t alg = 0;
-    for (;;) {
-        uint64_t start = 0;
-        if (lane == 0) start = atomicAdd(counter, (unsigned long long)grab);
-        start = ((uint64_t)uniform((uint32_t)(start >> 32)) << 32) | uniform((uint32_t)start);
-        if (start >= total) break;
+    for (uint64_t start = batch_first_take(grab); start < total;
+         start = batch_next_take(counter, grab, total, lane)) {
         const uint64_t stop = std::min<uint64_t>(total, start + grab);
         for (uint32_t cur = batch_find(items, n_items, start); cur < n_items && items[cur].tile0 < stop; ++cur) {
             const BatchItem& it = items[cur];

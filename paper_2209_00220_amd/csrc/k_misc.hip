@@ -45,12 +45,20 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 
 __global__ __launch_bounds__(kBlock) void k_bv_popcount(const uint64_t* __restrict__ bv, uint64_t n,
                                                         unsigned long long* __restrict__ count) {
+    __shared__ uint32_t part[kWavesPerBlock];
     const uint64_t nwords = (n + 63) >> 6;
     uint32_t s = 0;
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += (uint64_t)gridDim.x * blockDim.x)
         s += __builtin_popcountll(bv[w] & valid_mask(w, n));
     s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd(count, (unsigned long long)s);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    // one atomic per block: same-address atomics serialise
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int i = 0; i < kWavesPerBlock; ++i) t += part[i];
+        if (t) atomicAdd(count, (unsigned long long)t);
+    }
 }
 
 // ------------------------------------------------------------ compaction
@@ -442,7 +450,8 @@ int bst_bv_popcount(const uint64_t* bv, uint64_t n_rows, uint64_t* dev_count, vo
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, (unsigned long long*)dev_count, 1);
     if (n_rows)
-        hipLaunchKernelGGL(k_bv_popcount, dim3(elem_grid((n_rows + 63) / 64)), dim3(kBlock), 0, st, bv, n_rows,
+        hipLaunchKernelGGL(k_bv_popcount, dim3(std::min<uint32_t>(elem_grid((n_rows + 63) / 64), (uint32_t)props().cus * 2)),
+                           dim3(kBlock), 0, st, bv, n_rows,
                            (unsigned long long*)dev_count);
     return hip_check(hipGetLastError(), "popcount launch");
 }

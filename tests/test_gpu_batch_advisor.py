@@ -120,3 +120,58 @@ def test_advisor_choice_consistent_with_oracle():
     name = {oadv.BITPACKED: "bitpacked", oadv.BYTESLICE: "byteslice", oadv.PPVBS: "ppvbs"}[want]
     assert res.chosen == name
     assert all(np.all(t > 0) for t in res.times.values())
+
+
+def test_batches_back_to_back_without_waits():
+    """Batches launched one after another with no host wait in between (their
+    work lists go through the library's pinned staging ring, wrapping it at
+    least twice), each freed right after its launch: every result is still
+    the plain scan."""
+    from paper_2209_00220_amd import _lib as L
+    from paper_2209_00220_amd.batch import Batch
+    from paper_2209_00220_amd.column import bv_to_numpy
+
+    rng = np.random.default_rng(21)
+    cols, xs = [], []
+    for i in range(4):
+        n = int(rng.integers(5_000, 40_000))
+        w = int(rng.integers(8, 25))
+        x = datagen.zipf_column(n, w, 1.0, seed=2100 + i)
+        xs.append(x)
+        cols.append(device_columns(x, w))
+    ops = ["lt", "le", "gt", "ge", "eq", "ne", "between"]
+    specs = []
+    for k in range(64):
+        ci = int(rng.integers(0, 4))
+        x = xs[ci]
+        a, b = sorted(int(v) for v in x[rng.integers(0, x.shape[0], size=2)])
+        op = ops[int(rng.integers(0, len(ops)))]
+        specs.append((ci, ["ppvbs", "byteslice", "bitpacked"][k % 3], op, a, b if op == "between" else None))
+    want = [scan_values_bv(xs[ci], op, a, b) for ci, lay, op, a, b in specs]
+    per_batch = 32
+    image = int(L.bst_batch_workspace_bytes(per_batch))
+    n_batches = 2 * (8 << 20) // image + 8
+    flush("%d batches of %d scans, %d-byte work lists" % (n_batches, per_batch, image))
+    try:
+        launched = []
+        for bi in range(n_batches):
+            pick = rng.integers(0, len(specs), size=per_batch)
+            outs = []
+            items = []
+            for j in pick:
+                ci, lay, op, a, b = specs[int(j)]
+                dc = cols[ci][lay][1]
+                outs.append(dc.new_bv())
+                items.append((dc, op, a, b, None))
+            bt = Batch(items, outs)
+            bt.launch(grid=0, tiles_per_grab=1, use_graph=False)
+            bt.close()
+            del bt
+            launched.append((pick, outs))
+        torch.cuda.synchronize()
+        for bi, (pick, outs) in enumerate(launched):
+            for j, o in zip(pick, outs):
+                assert np.array_equal(bv_to_numpy(o), want[int(j)]), (bi, specs[int(j)])
+    finally:
+        for c in cols:
+            close_columns(c)

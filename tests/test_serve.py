@@ -32,14 +32,24 @@ class HostExecutor:
             out[:] = scan_values(self.tables[t][c], op, lo, hi, in_mask=inb)
         if self.clock is not None:
             self.clock.t += self.step_cost
+        return object()
 
-    def counts(self, pairs):
+    def count_rows(self, pairs):
         return [int(bv.sum()) for _, bv in pairs]
+
+    def read_counts(self, handle):
+        return handle
 
     def lookup(self, t, c, bv, count):
         return self.tables[t][c][bv].copy()
 
-    def finish(self, values_list):
+    def fence(self):
+        return object()
+
+    def is_done(self, token):
+        return True
+
+    def wait(self, token):
         pass
 
 
@@ -130,15 +140,37 @@ def test_budget_limits_admission():
     qs = _queries(tables, 12, seed=5)
     per_query = 2 * 8 * ((5000 + 63) // 64)   # the larger table's two bitvectors
     ex = HostExecutor(tables)
-    srv = Server(ex, budget_bytes=3 * per_query)
+    srv = Server(ex, budget_bytes=6 * per_query)   # bitvectors may hold half: three queries
     res = srv.run(qs)
     assert len(res) == len(qs)
     assert max(len(s) for s in ex.steps) <= 3
     # bitvector reservations never exceed the budget (lookup bytes may, for the oldest query)
-    assert srv.in_use == 0
+    assert srv.in_use == 0 and srv.scan_in_use == 0
     # admission in arrival order
     adm = [res[q.qid].admitted for q in sorted(qs, key=lambda q: q.qid)]
     assert adm == sorted(adm)
+
+
+def test_lookups_keep_their_share_of_the_budget():
+    # one-predicate queries all arriving at once: the bitvectors of the admitted
+    # queries hold at most the scan share, so every query's lookup fits in the
+    # rest and it completes in the step its scan ran
+    tables = _tables()
+    clock = FakeClock()
+    qs = [q for q in _queries(tables, 40, seed=11) if q.table == "a"][:12]
+    for q in qs:
+        q.preds = q.preds[:1]
+    per_query = 2 * 8 * ((5000 + 63) // 64)
+    budget = 1 << 20
+    ex = HostExecutor(tables, step_cost=0.01, clock=clock)
+    srv = Server(ex, budget_bytes=budget, scan_share=4 * per_query / budget, clock=clock, sleep=clock.sleep)
+    res = srv.run(qs)
+    assert len(qs) == 12 and max(len(s) for s in ex.steps) == 4 and len(ex.steps) == 3
+    for q in qs:
+        assert res[q.qid].done == pytest.approx(res[q.qid].admitted + 0.01)
+        assert res[q.qid].count == _plain(tables, q)[1]
+    with pytest.raises(ValueError):
+        Server(ex, budget_bytes=budget, scan_share=0.0)
 
 
 def test_single_query_over_budget_still_runs():
