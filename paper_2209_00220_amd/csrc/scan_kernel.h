@@ -7,8 +7,17 @@
 namespace bst {
 namespace dev {
 
+// Waves per SIMD the variant is built for: 8 (at most 64 VGPRs, a few spilled)
+// hides more of the later levels' gather latency than the spills cost, except
+// for PP-VBS BETWEEN, whose two literals need more registers: it was fastest
+// built for 6 (74 VGPRs), ahead of 7 (72) and of 8 (spilling).
+template <int MODE, bool DENSE>
+constexpr int scan_waves() {
+    return (MODE == kModeBetween && !DENSE) ? kMinWaves : 8;
+}
+
 template <int MODE, int SHORT, bool DENSE, bool HAS_IN, bool COUNT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kMinWaves, 8))) void k_scan_slices(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(scan_waves<MODE, DENSE>(), 8))) void k_scan_slices(
     const DevCol c, const ScanLit lit, const uint64_t* __restrict__ in_mask, uint64_t* __restrict__ out,
     unsigned long long* __restrict__ counters) {
     __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerBlock][kWaveLds];
