@@ -115,6 +115,8 @@ struct TileData {
     uint32_t m2;    // PP-VBS: dword `lane` of the tile's 32 M_2 words (0 when unused)
     uint32_t m3;    // PP-VBS: the same of M_3 (0 when the column has no third byte)
     uint32_t in;    // dword `lane` of the tile's 32 incoming-mask words (all ones when none)
+    uint32_t dir2;  // PP-VBS: the directory entry of BS_2 at the tile's first row, where the
+                    // tile's run of BS_2 starts (the same in every lane)
 };
 
 // Raw buffer access (gfx9-family descriptor: no format, no swizzle).  A buffer
@@ -157,6 +159,14 @@ __device__ __forceinline__ TileData load_tile(const DevCol& c, const uint64_t* _
     d.q1 = buffer_load16(r1, lane * 32 + 16);
     d.m2 = DENSE ? 0u : load_mask_dword(c, 2, t, lane, valid);
     d.m3 = DENSE ? 0u : load_mask_dword(c, 3, t, lane, valid);
+    d.dir2 = 0;
+    if (!DENSE) {
+        // fetched with the tile, in the same in-order stream of vector loads: level
+        // 2's gathers then wait for nothing issued after the tile's own loads
+        const bool has = valid && c.K >= 2;
+        const void* base = has ? (const void*)(c.dir[2] + ((t * kTileRows) >> c.dir_shift)) : (const void*)c.bs[1];
+        d.dir2 = buffer_load4(buffer_rsrc(base, has ? 4u : 0u), 0);
+    }
     d.in = ~0u;
     if (HAS_IN) {
         // the mask has ceil(n/64) words; the last tile may hold fewer than 32
@@ -317,6 +327,43 @@ __device__ __forceinline__ uint32_t stage_run(const uint8_t* __restrict__ src, u
 // back its dword.  incl: inclusive lane prefix of the M_j dword popcounts
 // (PP-VBS); row_excl / total: this lane's exclusive prefix and the tile's total
 // of pending rows.
+// The byte rules of one level for one row: b is the row's byte, cl / ch the
+// literals' bytes at this level, plo / phi whether the row is still equal to the
+// lower / upper literal, more whether the row has a next byte, lo_open / hi_open
+// whether the literal goes on after this byte.  Returns flags: kRuleHit (found
+// in the tracked relation; BETWEEN: out of range), kRuleKeepLo / kRuleKeepHi
+// (still equal, and the row has a next byte) and kRuleEq (the byte equals a
+// literal's).  Flags rather than reference outputs: a store to one of two
+// locals chosen at run time would put them in scratch memory.
+constexpr uint32_t kRuleHit = 1, kRuleKeepLo = 2, kRuleKeepHi = 4, kRuleEq = 8;
+
+template <int MODE>
+__device__ __forceinline__ uint32_t row_rule(uint32_t b, uint32_t cl, uint32_t ch, bool plo, bool phi, bool more,
+                                             bool lo_open, bool hi_open) {
+    uint32_t f = 0;
+    if (plo) {
+        if (b == cl) f |= kRuleEq;
+        if (MODE == kModeLT || MODE == kModeBetween) {
+            if (b < cl) f |= kRuleHit;                                           // below
+            else if (b == cl && lo_open) f |= more ? kRuleKeepLo : kRuleHit;     // a prefix: below
+        } else if (MODE == kModeGT) {
+            if (b > cl) f |= kRuleHit;                                           // above
+            else if (b == cl && more) f |= lo_open ? kRuleKeepLo : kRuleHit;     // equal, then more: above
+        } else {
+            if (b == cl) {                                                       // equal over the literal
+                if (lo_open) f |= more ? kRuleKeepLo : 0u;
+                else f |= more ? 0u : kRuleHit;
+            }
+        }
+    }
+    if (MODE == kModeBetween && phi) {
+        if (b == ch) f |= kRuleEq;
+        if (b > ch) f |= kRuleHit;                                               // above the upper literal
+        else if (b == ch && more) f |= hi_open ? kRuleKeepHi : kRuleHit;
+    }
+    return f;
+}
+
 template <int MODE, bool DENSE, bool COUNT>
 __device__ __forceinline__ void sparse_level(const DevCol& c, const ScanLit& lit, uint64_t t, uint32_t j,
                                              uint64_t run0, uint32_t cur_mv, uint32_t next_mv, uint32_t incl,
@@ -361,24 +408,8 @@ __device__ __forceinline__ void sparse_level(const DevCol& c, const ScanLit& lit
             const bool plo = (plo_w >> bit) & 1, phi = (phi_w >> bit) & 1;
             const bool more = j < K && (DENSE || ((nxt_w >> bit) & 1));   // the row has a byte j+1
             const bool lo_open = j < lit.llo, hi_open = j < lit.lhi;      // the literal goes on after byte j
-            bool hit = false, keep_lo = false, keep_hi = false, eqb = false;
-            if (plo) {
-                eqb = b == cl;
-                if (MODE == kModeLT || MODE == kModeBetween) {
-                    if (b < cl) hit = true;                                  // below
-                    else if (b == cl && lo_open) { if (more) keep_lo = true; else hit = true; }   // prefix: below
-                } else if (MODE == kModeGT) {
-                    if (b > cl) hit = true;                                  // above
-                    else if (b == cl) { if (lo_open) keep_lo = more; else hit = more; }   // equal, then more: above
-                } else {
-                    if (b == cl) { if (lo_open) keep_lo = more; else hit = !more; }       // equal over the literal
-                }
-            }
-            if (MODE == kModeBetween && phi) {
-                eqb = eqb || b == ch;
-                if (b > ch) hit = true;                                      // above the upper literal
-                else if (b == ch) { if (hi_open) keep_hi = more; else hit = hit || more; }
-            }
+            const uint32_t f = row_rule<MODE>(b, cl, ch, plo, phi, more, lo_open, hi_open);
+            const bool hit = f & kRuleHit, keep_lo = f & kRuleKeepLo, keep_hi = f & kRuleKeepHi, eqb = f & kRuleEq;
             const uint32_t m = 1u << bit;
             if (hit) atomicOr(&sp->hit[jd], m);
             if (keep_lo) atomicOr(&sp->lo[jd], m);
@@ -570,7 +601,8 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
             runlen = kTileRows;
         } else {
             incl = both >> 16;
-            run0 = c.dir[j][(t * kTileRows) >> c.dir_shift];
+            run0 = j == 2 ? (uint32_t)__builtin_amdgcn_readfirstlane((int)td.dir2)
+                          : c.dir[j][(t * kTileRows) >> c.dir_shift];
             runlen = (uint32_t)__builtin_amdgcn_readlane((int)both, 63) >> 16;
         }
         // few pending rows: one row per lane and round
