@@ -762,10 +762,25 @@ __device__ __forceinline__ void scan_slices_range(const DevCol& c, const ScanLit
                                                   uint64_t stride, uint32_t lane, uint8_t* lds, Stats& st) {
     if (t_begin >= t_end) return;
     uint64_t t = t_begin;
+    const uint64_t mine = (t_end - t_begin + stride - 1) / stride;
+    if constexpr (!DENSE && SHORT == 0 && MODE != kModeBetween) {
+        // PP-VBS with a multi-byte literal: two tiles in flight, so that the later
+        // levels' working set fits the registers of 8 waves per SIMD unspilled
+        TileData a = load_tile<DENSE, HAS_IN>(c, in_mask, t, lane);
+        TileData b = load_tile<DENSE, HAS_IN>(c, in_mask, t + stride, lane, t + stride < t_end);
+        for (uint64_t i = 0; i < mine; i += 2) {
+            process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, a, lds, st, t_end);
+            a = load_tile<DENSE, HAS_IN>(c, in_mask, t + 2 * stride, lane, t + 2 * stride < t_end);
+            t += stride;
+            process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, b, lds, st, t_end);
+            b = load_tile<DENSE, HAS_IN>(c, in_mask, t + 2 * stride, lane, t + 2 * stride < t_end);
+            t += stride;
+        }
+        return;
+    }
     TileData a = load_tile<DENSE, HAS_IN>(c, in_mask, t, lane);
     TileData b = load_tile<DENSE, HAS_IN>(c, in_mask, t + stride, lane, t + stride < t_end);
     TileData d = load_tile<DENSE, HAS_IN>(c, in_mask, t + 2 * stride, lane, t + 2 * stride < t_end);
-    const uint64_t mine = (t_end - t_begin + stride - 1) / stride;
     for (uint64_t i = 0; i < mine; i += 3) {
         process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, a, lds, st, t_end);
         a = load_tile<DENSE, HAS_IN>(c, in_mask, t + 3 * stride, lane, t + 3 * stride < t_end);

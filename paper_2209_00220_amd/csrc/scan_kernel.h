@@ -8,10 +8,10 @@ namespace bst {
 namespace dev {
 
 // Waves per SIMD the variant is built for: 8 (at most 64 VGPRs, a few spilled)
-// hides more of the later levels' gather latency than the spills cost (PP-VBS
-// '<' with a multi-byte literal: faster at 8 with 36 bytes spilled than at 7
-// with none), except for PP-VBS BETWEEN, whose two literals need more
-// registers: it was fastest built for 6 (77 VGPRs), ahead of 7 and of 8.
+// hides more of the later levels' gather latency than fewer waves do (PP-VBS
+// '<' with a multi-byte literal keeps two tiles in flight instead of three to
+// fit), except for PP-VBS BETWEEN, whose two literals need more registers: it
+// was fastest built for 6 (77 VGPRs, three tiles in flight), ahead of 7 and 8.
 template <int MODE, bool DENSE>
 constexpr int scan_waves() {
     return (MODE == kModeBetween && !DENSE) ? kMinWaves : 8;
