@@ -319,12 +319,12 @@ __device__ __forceinline__ uint32_t stage_run(const uint8_t* __restrict__ src, u
 
 // One level for a tile with at most kSparseRows pending rows: one row per lane
 // and round of 64.  The pending rows (bits of plov | phiv) are listed in LDS;
-// each lane takes one per round,
-// finds its byte j (PP-VBS: the directory entry plus the M_j popcounts before
-// it; ByteSlice: its place in the tile-interleaved slice), gathers it, applies
-// the byte and length rules of the level to that row alone, and sets the row's
-// bits in the per-dword outcome arrays with LDS atomics; every lane then reads
-// back its dword.  incl: inclusive lane prefix of the M_j dword popcounts
+// each lane takes one per round and finds its byte j (PP-VBS: the directory
+// entry plus the M_j popcounts before it; ByteSlice: its place in the
+// tile-interleaved slice).  The gathers of all rounds are issued first; then,
+// round by round, each lane applies the byte and length rules of the level to
+// its row alone and sets the row's bits in the per-dword outcome arrays with
+// LDS atomics; every lane then reads back its dword.  incl: inclusive lane prefix of the M_j dword popcounts
 // (PP-VBS); row_excl / total: this lane's exclusive prefix and the tile's total
 // of pending rows.
 // The byte rules of one level for one row: b is the row's byte, cl / ch the
@@ -384,39 +384,54 @@ __device__ __forceinline__ void sparse_level(const DevCol& c, const ScanLit& lit
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (uint32_t base = 0; base < total; base += 64) {
-        // every lane runs the cross-lane reads (lanes past `total` on entry 0)
-        const uint32_t ent = base + lane;
-        const uint32_t e = ent < total ? (uint32_t)sp->list[ent] : 0u;
-        const uint32_t jd = e >> 5, bit = e & 31, k = jd >> 1;
-        const uint32_t below = (1u << bit) - 1u;
-        const uint32_t plo_w = __shfl(plov, (int)jd, 64), phi_w = __shfl(phiv, (int)jd, 64);
-        const uint32_t nxt_w = __shfl(next_mv, (int)jd, 64);
-        uint32_t pos;
-        if (DENSE) {
-            pos = (((jd & 1) << 5) | bit) * 32 + k;   // tile-interleaved: lane-in-group * 32 + group
-        } else {
-            const uint32_t mlo = __shfl(cur_mv, (int)(2 * k), 64);
-            const uint32_t mhi = __shfl(cur_mv, (int)(2 * k + 1), 64);
-            const uint32_t before = __shfl(incl, (int)(k ? 2 * k - 1 : 0), 64);
-            pos = (k ? before : 0u) + ((jd & 1) ? (uint32_t)__builtin_popcount(mlo) : 0u) +
-                  (uint32_t)__builtin_popcount(((jd & 1) ? mhi : mlo) & below);
+    // All rounds' gathers are issued before any is used, so the tile waits for
+    // one gather however many rounds it has; the rules then run round by round.
+    constexpr int kRounds = kSparseRows / 64;
+    uint32_t bb[kRounds];
+    Unroll<0, kRounds>::run([&](auto rc) {
+        constexpr uint32_t r = decltype(rc)::value;
+        bb[r] = 0;
+        if (r * 64 < total) {
+            // every lane runs the cross-lane reads (lanes past `total` on entry 0)
+            const uint32_t ent = r * 64 + lane;
+            const uint32_t e = ent < total ? (uint32_t)sp->list[ent] : 0u;
+            const uint32_t jd = e >> 5, bit = e & 31, k = jd >> 1;
+            const uint32_t below = (1u << bit) - 1u;
+            uint32_t pos;
+            if (DENSE) {
+                pos = (((jd & 1) << 5) | bit) * 32 + k;   // tile-interleaved: lane-in-group * 32 + group
+            } else {
+                const uint32_t mlo = __shfl(cur_mv, (int)(2 * k), 64);
+                const uint32_t mhi = __shfl(cur_mv, (int)(2 * k + 1), 64);
+                const uint32_t before = __shfl(incl, (int)(k ? 2 * k - 1 : 0), 64);
+                pos = (k ? before : 0u) + ((jd & 1) ? (uint32_t)__builtin_popcount(mlo) : 0u) +
+                      (uint32_t)__builtin_popcount(((jd & 1) ? mhi : mlo) & below);
+            }
+            if (ent < total) bb[r] = c.bs[j][run0 + pos];
         }
-        if (ent < total) {
-            const uint32_t b = c.bs[j][run0 + pos];
-            const uint32_t cl = lit_byte(lit.lo, j), ch = lit_byte(lit.hi, j);
-            const bool plo = (plo_w >> bit) & 1, phi = (phi_w >> bit) & 1;
-            const bool more = j < K && (DENSE || ((nxt_w >> bit) & 1));   // the row has a byte j+1
-            const bool lo_open = j < lit.llo, hi_open = j < lit.lhi;      // the literal goes on after byte j
-            const uint32_t f = row_rule<MODE>(b, cl, ch, plo, phi, more, lo_open, hi_open);
-            const bool hit = f & kRuleHit, keep_lo = f & kRuleKeepLo, keep_hi = f & kRuleKeepHi, eqb = f & kRuleEq;
-            const uint32_t m = 1u << bit;
-            if (hit) atomicOr(&sp->hit[jd], m);
-            if (keep_lo) atomicOr(&sp->lo[jd], m);
-            if (keep_hi) atomicOr(&sp->hi[jd], m);
-            if (COUNT && eqb) atomicOr(&sp->eq[jd], m);
+    });
+    const uint32_t cl = lit_byte(lit.lo, j), ch = lit_byte(lit.hi, j);
+    const bool lo_open = j < lit.llo, hi_open = j < lit.lhi;   // the literal goes on after byte j
+    Unroll<0, kRounds>::run([&](auto rc) {
+        constexpr uint32_t r = decltype(rc)::value;
+        if (r * 64 < total) {
+            const uint32_t ent = r * 64 + lane;
+            const uint32_t e = ent < total ? (uint32_t)sp->list[ent] : 0u;
+            const uint32_t jd = e >> 5, bit = e & 31;
+            const uint32_t plo_w = __shfl(plov, (int)jd, 64), phi_w = __shfl(phiv, (int)jd, 64);
+            const uint32_t nxt_w = __shfl(next_mv, (int)jd, 64);
+            if (ent < total) {
+                const bool plo = (plo_w >> bit) & 1, phi = (phi_w >> bit) & 1;
+                const bool more = j < K && (DENSE || ((nxt_w >> bit) & 1));   // the row has a byte j+1
+                const uint32_t f = row_rule<MODE>(bb[r], cl, ch, plo, phi, more, lo_open, hi_open);
+                const uint32_t m = 1u << bit;
+                if (f & kRuleHit) atomicOr(&sp->hit[jd], m);
+                if (f & kRuleKeepLo) atomicOr(&sp->lo[jd], m);
+                if (f & kRuleKeepHi) atomicOr(&sp->hi[jd], m);
+                if (COUNT && (f & kRuleEq)) atomicOr(&sp->eq[jd], m);
+            }
         }
-    }
+    });
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
