@@ -482,8 +482,8 @@ __device__ __forceinline__ uint32_t level_mask_vec(uint32_t& plov, uint32_t& phi
 template <int MODE, int SHORT, bool DENSE, bool HAS_IN, bool COUNT>
 __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit, uint64_t* __restrict__ out,
                                              uint64_t t, uint32_t lane, const TileData& td, uint8_t* lds,
-                                             Stats& st, uint64_t t_end) {
-    if (t >= t_end) return;   // past the wave's last tile (a prefetch slot with nothing to do)
+                                             Stats& st, bool live) {
+    if (!live) return;   // past the wave's last tile (a prefetch slot with nothing to do)
     const uint64_t w0 = t * 32;
     const uint32_t K = c.K;
     const uint32_t clo = lit_byte(lit.lo, 1), chi = lit_byte(lit.hi, 1);
@@ -491,7 +491,10 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
     // rows this lane's result dword may report: selected by the incoming mask and
     // inside the column
     const uint64_t d = w0 * 2 + lane;
-    const bool full = (t + 1) * kTileRows <= c.n;
+    // 32-bit compare of uniform values (tile indices fit: directory entries are
+    // 32-bit): a 64-bit one needs a vector register for one side on this chip,
+    // which is then held, or spilled, across the whole loop
+    const bool full = (uint32_t)t < (uint32_t)(c.n / kTileRows);
     uint32_t actv = HAS_IN ? td.in : ~0u;
     if (!full) {
         const uint64_t r0 = d * 32;
@@ -759,8 +762,11 @@ __device__ __forceinline__ void process_tile(const DevCol& c, const ScanLit& lit
         pend = pend_next;
         cur_mv = next_mv;
     }
-    if (MODE != kModeBetween && lit.negate) outv = actv & ~outv;
-    else outv &= actv;
+    // negation as a xor with a mask held in a scalar register (built in a vector
+    // register it is kept, or spilled, across the whole loop)
+    const uint32_t neg =
+        MODE != kModeBetween ? (uint32_t)__builtin_amdgcn_readfirstlane((int)(lit.negate ? ~0u : 0u)) : 0u;
+    outv = (outv ^ neg) & actv;
     if (full || d < ((c.n + 63) >> 6) * 2) reinterpret_cast<uint32_t*>(out)[d] = outv;
 }
 
@@ -777,34 +783,37 @@ __device__ __forceinline__ void scan_slices_range(const DevCol& c, const ScanLit
                                                   uint64_t stride, uint32_t lane, uint8_t* lds, Stats& st) {
     if (t_begin >= t_end) return;
     uint64_t t = t_begin;
-    const uint64_t mine = (t_end - t_begin + stride - 1) / stride;
+    // 32-bit uniform counters decide which slots hold a tile: a 64-bit bound kept
+    // live across the loop ended up in vector registers and spilled, and each
+    // reload from scratch waited for every load in flight
+    const uint32_t mine = (uint32_t)((t_end - t_begin + stride - 1) / stride);
     if constexpr (!DENSE && SHORT == 0 && MODE != kModeBetween) {
         // PP-VBS with a multi-byte literal: two tiles in flight, so that the later
-        // levels' working set fits the registers of 8 waves per SIMD unspilled
+        // levels' working set fits the registers of 8 waves per SIMD
         TileData a = load_tile<DENSE, HAS_IN>(c, in_mask, t, lane);
-        TileData b = load_tile<DENSE, HAS_IN>(c, in_mask, t + stride, lane, t + stride < t_end);
-        for (uint64_t i = 0; i < mine; i += 2) {
-            process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, a, lds, st, t_end);
-            a = load_tile<DENSE, HAS_IN>(c, in_mask, t + 2 * stride, lane, t + 2 * stride < t_end);
+        TileData b = load_tile<DENSE, HAS_IN>(c, in_mask, t + stride, lane, 1 < mine);
+        for (uint32_t i = 0; i < mine; i += 2) {
+            process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, a, lds, st, true);
+            a = load_tile<DENSE, HAS_IN>(c, in_mask, t + 2 * stride, lane, i + 2 < mine);
             t += stride;
-            process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, b, lds, st, t_end);
-            b = load_tile<DENSE, HAS_IN>(c, in_mask, t + 2 * stride, lane, t + 2 * stride < t_end);
+            process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, b, lds, st, i + 1 < mine);
+            b = load_tile<DENSE, HAS_IN>(c, in_mask, t + 2 * stride, lane, i + 3 < mine);
             t += stride;
         }
         return;
     }
     TileData a = load_tile<DENSE, HAS_IN>(c, in_mask, t, lane);
-    TileData b = load_tile<DENSE, HAS_IN>(c, in_mask, t + stride, lane, t + stride < t_end);
-    TileData d = load_tile<DENSE, HAS_IN>(c, in_mask, t + 2 * stride, lane, t + 2 * stride < t_end);
-    for (uint64_t i = 0; i < mine; i += 3) {
-        process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, a, lds, st, t_end);
-        a = load_tile<DENSE, HAS_IN>(c, in_mask, t + 3 * stride, lane, t + 3 * stride < t_end);
+    TileData b = load_tile<DENSE, HAS_IN>(c, in_mask, t + stride, lane, 1 < mine);
+    TileData d = load_tile<DENSE, HAS_IN>(c, in_mask, t + 2 * stride, lane, 2 < mine);
+    for (uint32_t i = 0; i < mine; i += 3) {
+        process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, a, lds, st, true);
+        a = load_tile<DENSE, HAS_IN>(c, in_mask, t + 3 * stride, lane, i + 3 < mine);
         t += stride;
-        process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, b, lds, st, t_end);
-        b = load_tile<DENSE, HAS_IN>(c, in_mask, t + 3 * stride, lane, t + 3 * stride < t_end);
+        process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, b, lds, st, i + 1 < mine);
+        b = load_tile<DENSE, HAS_IN>(c, in_mask, t + 3 * stride, lane, i + 4 < mine);
         t += stride;
-        process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, d, lds, st, t_end);
-        d = load_tile<DENSE, HAS_IN>(c, in_mask, t + 3 * stride, lane, t + 3 * stride < t_end);
+        process_tile<MODE, SHORT, DENSE, HAS_IN, COUNT>(c, lit, out, t, lane, d, lds, st, i + 2 < mine);
+        d = load_tile<DENSE, HAS_IN>(c, in_mask, t + 3 * stride, lane, i + 5 < mine);
         t += stride;
     }
 }
