@@ -212,3 +212,43 @@ def test_repeatable():
                 assert np.array_equal(_bv(col.scan("between", 1000, 900_000)), a), lay
     finally:
         close_columns(cols)
+
+
+@pytest.mark.parametrize("grid,stage_pct", [(1, 0), (3, 1), (3, 100)])
+def test_scan_parity_many_tiles_per_wave(grid, stage_pct):
+    """A tiny launch (grid workgroups of 4 waves) gives each wave from two to
+    nine tiles, odd and even counts, so every prefetch slot of the tile
+    rotation holds a tile at some point and the slots past a wave's last tile
+    are exercised; the staging threshold switches later levels between the
+    staged run (1 %: any pending group) and group gathers (0: never staged;
+    100 %: only when every group is pending)."""
+    from paper_2209_00220_amd import _lib as L
+    from paper_2209_00220_amd.column import bv_from_numpy
+
+    flush("scan parity with grid=%d stage_pct=%d" % (grid, stage_pct))
+    saved = (L.bst_tune_get(L.TUNE_SCAN_GRID), L.bst_tune_get(L.TUNE_STAGE_PCT))
+    L.bst_tune_set(L.TUNE_SCAN_GRID, grid)
+    L.bst_tune_set(L.TUNE_STAGE_PCT, stage_pct)
+    try:
+        for n, w, s in ((2048 * 9 + 5, 20, 1.0), (2048 * 14, 16, 0.5), (70_001, 24, 1.2)):
+            x = datagen.zipf_column(n, w, s, seed=3 * n + w)
+            A, _, _ = build_dictionary(x)
+            cols = device_columns(x, w)
+            mask_np = datagen.random_mask_words(n, seed=n + 7, density=0.5)
+            mask_t = bv_from_numpy(mask_np)
+            mask_rows = unpack_bits(mask_np, n)
+            lits = literal_set(A, w)[::2]
+            try:
+                for lay, (hc, col) in cols.items():
+                    for op in ("lt", "gt", "eq", "ne", "between"):
+                        for i, lo in enumerate(lits):
+                            hi = lits[(i * 5 + 3) % len(lits)] if op == "between" else None
+                            for msk in (None, mask_t):
+                                got = _bv(col.scan(op, lo, hi, in_mask=msk))
+                                want = scan_values_bv(x, op, lo, hi, None if msk is None else mask_rows)
+                                assert np.array_equal(got, want), (n, lay, op, lo, hi, msk is not None)
+            finally:
+                close_columns(cols)
+    finally:
+        L.bst_tune_set(L.TUNE_SCAN_GRID, saved[0])
+        L.bst_tune_set(L.TUNE_STAGE_PCT, saved[1])
