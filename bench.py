@@ -20,7 +20,7 @@ Other workloads print their own line: ``--workload wide`` (16-column table:
 layout advisor per column, pipelined conjunction, lookups),
 ``--workload batch`` (256 predicates over 64 columns in one launch),
 ``--workload serve`` (continuous batching over resident tables) and
-``--workload sweep`` (skew and domain sensitivity).
+``--workload sweep`` (skew, domain and Gaussian-variance sensitivity).
 """
 from __future__ import annotations
 
@@ -412,8 +412,9 @@ def serve_main(args):
 
 
 def sweep_main(args):
-    """Skew and domain sensitivity: per (Zipf s, width w) the bytes per row of each
-    layout and its '<' (about 10 %) and '=' (most frequent value) scan rates."""
+    """Skew, domain and distribution sensitivity: per (Zipf s, width w), and per
+    (Gaussian sigma, width w), the bytes per row of each layout and its '<'
+    (about 10 %) and '=' (most frequent value) scan rates."""
     import numpy as np
     import torch
 
@@ -424,33 +425,47 @@ def sweep_main(args):
     torch.cuda.set_device(0)
     n = args.sweep_rows
     rows = []
+
+    def point(x, w, rec, label):
+        v, k = workloads.value_counts(x, w)
+        lt = workloads.lit_lt(v, k, 0.10)[0]
+        eq = int(v[int(np.argmax(k))])
+        d = Dictionary(x)
+        rec["distinct"] = int(v.shape[0])
+        for lay in LAYOUTS:
+            hc = HostColumn.encode(d, lay, width=0 if lay == "ppvbs" else w)
+            col = DeviceColumn(hc)
+            out = col.new_bv()
+            t_lt = _ms_events(lambda: col.scan("lt", lt, out=out))
+            t_eq = _ms_events(lambda: col.scan("eq", eq, out=out))
+            rec[lay] = {"bits_per_row": round(8 * hc.info.layout_bytes / n, 3),
+                        "lt_gtuples": round(n / (t_lt * 1e-3) / 1e9, 1),
+                        "eq_gtuples": round(n / (t_eq * 1e-3) / 1e9, 1)}
+            col.close()
+            hc.close()
+        d.close()
+        rows.append(rec)
+        progress(label + "  " + "  ".join(
+            "%s %.1f b/row lt %.0f eq %.0f" % (l, rec[l]["bits_per_row"], rec[l]["lt_gtuples"], rec[l]["eq_gtuples"])
+            for l in LAYOUTS))
+
     for s in (0.0, 0.5, 1.0, 1.5, 2.0):
         for w in (4, 8, 12, 16, 20, 24):
             x = datagen.zipf_column(n, w, s, seed=1000 + int(10 * s) * 100 + w)
-            v, k = workloads.value_counts(x, w)
-            lt = workloads.lit_lt(v, k, 0.10)[0]
-            eq = int(v[int(np.argmax(k))])
-            d = Dictionary(x)
-            rec = {"s": s, "w": w, "distinct": int(v.shape[0])}
-            for lay in LAYOUTS:
-                hc = HostColumn.encode(d, lay, width=0 if lay == "ppvbs" else w)
-                col = DeviceColumn(hc)
-                out = col.new_bv()
-                t_lt = _ms_events(lambda: col.scan("lt", lt, out=out))
-                t_eq = _ms_events(lambda: col.scan("eq", eq, out=out))
-                rec[lay] = {"bits_per_row": round(8 * hc.info.layout_bytes / n, 3),
-                            "lt_gtuples": round(n / (t_lt * 1e-3) / 1e9, 1),
-                            "eq_gtuples": round(n / (t_eq * 1e-3) / 1e9, 1)}
-                col.close()
-                hc.close()
-            d.close()
-            rows.append(rec)
-            progress("s=%.1f w=%d  " % (s, w) + "  ".join(
-                "%s %.1f b/row lt %.0f eq %.0f" % (l, rec[l]["bits_per_row"], rec[l]["lt_gtuples"], rec[l]["eq_gtuples"])
-                for l in LAYOUTS))
-    out = {"metric": "scan Gtuples/s and bits/row per layout across Zipf skew and domain width",
+            point(x, w, {"dist": "zipf", "s": s, "w": w}, "zipf s=%.1f w=%d" % (s, w))
+            del x
+    # Gaussian columns of growing variance (sigma = 2^(w/4), 2^(w/2), 2^(3w/4))
+    for w in (12, 20):
+        for q in (1, 2, 3):
+            sigma = 2.0 ** (q * w / 4.0)
+            x = datagen.gaussian_column(n, w, sigma, seed=7000 + 10 * w + q)
+            point(x, w, {"dist": "gaussian", "sigma": round(sigma, 1), "w": w},
+                  "gaussian sigma=2^%.0f w=%d" % (q * w / 4.0, w))
+            del x
+    out = {"metric": "scan Gtuples/s and bits/row per layout across Zipf skew, domain width and Gaussian variance",
            "unit": "Gtuples/s", "n_gpus": 1, "dtype": "u8", "data": "synthetic",
-           "config": {"workload": "%d rows per column; Zipf s in {0..2}, width w in {4..24}" % n, "rows": n},
+           "config": {"workload": "%d rows per column; Zipf s in {0..2} x width w in {4..24}; Gaussian "
+                                  "sigma in {2^(w/4), 2^(w/2), 2^(3w/4)} x w in {12, 20}" % n, "rows": n},
            "points": rows}
     print(json.dumps(out), flush=True)
 
@@ -462,7 +477,7 @@ def main():
                     help="scan: the one-column benchmark (default); wide: 16-column table with the advisor, "
                          "a conjunction and lookups; batch: 256 predicates over 64 columns in one launch; "
                          "serve: continuous batching over resident tables; "
-                         "sweep: skew x domain sensitivity of every layout")
+                         "sweep: skew x domain (and Gaussian variance) sensitivity of every layout")
     ap.add_argument("--serve-tables", type=int, default=8)
     ap.add_argument("--serve-rows-lo", type=float, default=1e6)
     ap.add_argument("--serve-rows-hi", type=float, default=1e8)

@@ -77,6 +77,16 @@ def zipf_column(n: int, w: int, s: float, seed: int, mapping: int = SCATTER,
     return out
 
 
+def gaussian_column(n: int, w: int, sigma: float, seed: int) -> np.ndarray:
+    """n uint32 values: a normal distribution centred in [0, 2^w) with standard
+    deviation sigma, rounded to integers and clipped to the domain (numpy's
+    seeded PCG64 generator)."""
+    rng = np.random.Generator(np.random.PCG64(int(seed) & (2**64 - 1)))
+    hi = float((1 << int(w)) - 1)
+    x = rng.normal(loc=float(1 << (int(w) - 1)), scale=float(sigma), size=int(n))
+    return np.clip(np.rint(x), 0.0, hi).astype(np.uint32)
+
+
 def uniform_ids(m: int, bound: int, seed: int) -> np.ndarray:
     """m uint32 integers uniform in [0, bound) (row IDs drawn with replacement)."""
     out = np.empty(int(m), dtype=np.uint32)

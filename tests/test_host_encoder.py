@@ -28,6 +28,7 @@ def _columns():
     yield "unif24", datagen.zipf_column(150_000, 24, 0.0, seed=6)
     yield "zipf32", datagen.zipf_column(120_000, 32, 1.5, seed=7)   # sort-based dictionary
     yield "wide65791", np.arange(255 + 256 * 255 + 1, dtype=np.uint32)
+    yield "gauss20", datagen.gaussian_column(200_000, 20, 2.0 ** 10, seed=8)
 
 
 @pytest.mark.parametrize("name,x", list(_columns()), ids=[c[0] for c in _columns()])
@@ -177,4 +178,15 @@ def test_categorical_codes(L, name, x):
             L.bst_free_host(h)
     finally:
         L.bst_dict_free(d)
+
+
+def test_gaussian_column_generator():
+    """Seeded, inside the domain, and spread by sigma (the sweep's input)."""
+    a = datagen.gaussian_column(400_000, 12, 64.0, seed=3)
+    b = datagen.gaussian_column(400_000, 12, 64.0, seed=3)
+    c = datagen.gaussian_column(400_000, 12, 64.0, seed=4)
+    assert a.dtype == np.uint32 and np.array_equal(a, b) and not np.array_equal(a, c)
+    assert a.max() < 4096 and abs(float(a.mean()) - 2048.0) < 1.0 and abs(float(a.std()) - 64.0) < 1.0
+    wide = datagen.gaussian_column(100_000, 8, 1e6, seed=5)   # clipped to [0, 255]
+    assert wide.min() == 0 and wide.max() == 255
 
