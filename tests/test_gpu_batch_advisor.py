@@ -175,3 +175,57 @@ def test_batches_back_to_back_without_waits():
     finally:
         for c in cols:
             close_columns(c)
+
+
+def test_batch_larger_than_staging_ring():
+    """A work list larger than the pinned staging ring goes up by a synchronous
+    copy instead; results are the plain scans, and a small batch launched right
+    after still goes through the ring."""
+    from paper_2209_00220_amd import _lib as L
+    from paper_2209_00220_amd.batch import Batch
+    from paper_2209_00220_amd.column import bv_to_numpy
+
+    rng = np.random.default_rng(31)
+    xs, cols = [], []
+    for i in range(3):
+        x = datagen.zipf_column(3000 + 777 * i, 16, 1.0, seed=3100 + i)
+        xs.append(x)
+        cols.append(device_columns(x, 16))
+    ops = ["lt", "ge", "eq", "between"]
+    specs = []
+    for k in range(48):
+        ci = k % 3
+        x = xs[ci]
+        a, b = sorted(int(v) for v in x[rng.integers(0, x.shape[0], size=2)])
+        op = ops[k % len(ops)]
+        specs.append((ci, ["ppvbs", "byteslice", "bitpacked"][(k // 3) % 3], op, a, b if op == "between" else None))
+    want = [scan_values_bv(xs[ci], op, a, b) for ci, lay, op, a, b in specs]
+    item_bytes = int(L.bst_batch_workspace_bytes(1) - L.bst_batch_workspace_bytes(0))
+    n_items = (8 << 20) // item_bytes + 700
+    flush("one batch of %d scans (%d-byte work list)" % (n_items, int(L.bst_batch_workspace_bytes(n_items))))
+    try:
+        pick = rng.integers(0, len(specs), size=n_items)
+        items, outs = [], []
+        for j in pick:
+            ci, lay, op, a, b = specs[int(j)]
+            dc = cols[ci][lay][1]
+            items.append((dc, op, a, b, None))
+            outs.append(dc.new_bv())
+        big = Batch(items, outs)
+        for rep in range(2):
+            for o in outs[:: max(1, n_items // 50)]:
+                o.fill_(-1)
+            big.launch(grid=0, tiles_per_grab=0, use_graph=False)
+            small_outs = [cols[0]["ppvbs"][1].new_bv() for _ in range(4)]
+            small = Batch([(cols[0]["ppvbs"][1], "lt", int(xs[0][i]), None, None) for i in range(4)], small_outs)
+            small.launch(grid=0, tiles_per_grab=1, use_graph=False)
+            small.close()
+            torch.cuda.synchronize()
+            for i, o in enumerate(small_outs):
+                assert np.array_equal(bv_to_numpy(o), scan_values_bv(xs[0], "lt", int(xs[0][i]), None))
+            for j, o in zip(pick, outs):
+                assert np.array_equal(bv_to_numpy(o), want[int(j)]), (rep, specs[int(j)])
+        big.close()
+    finally:
+        for c in cols:
+            close_columns(c)
