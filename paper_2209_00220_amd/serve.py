@@ -26,8 +26,8 @@ resident in device memory.  The server runs in steps:
 The loop never waits for the device while it has work to enqueue: each step
 and each set of lookups is followed by a fence (an event on the stream), the
 host reads counts and completes queries once their fences have passed, and
-keeps at most ``lookahead`` scan steps in flight so that new arrivals join
-soon.  So the host's admission, counting and lookup set-up of some queries
+keeps few scan steps in flight -- at most ``lookahead`` of them, covering at
+most ``lookahead_rows`` rows -- so that new arrivals join soon.  So the host's admission, counting and lookup set-up of some queries
 overlap the device's scans of others.
 
 Latency is completion time minus arrival time.  ``run_serial`` serves the
@@ -96,21 +96,24 @@ class Server:
     scan_share: fraction of the budget the bitvectors of admitted queries may
     hold; the rest is kept for lookups.
     max_batch: most scans per step.  step_rows: a step takes no further query
-    once its scans cover this many rows.  lookahead: most scan steps in flight.
+    once its scans cover this many rows.  lookahead / lookahead_rows: most scan
+    steps, and most rows scanned by them, in flight (one step always may be).
     """
 
     def __init__(self, executor, budget_bytes: int, max_batch: int = 256, scan_share: float = 0.5,
-                 step_rows: int = 1 << 27, lookahead: int = 2,
+                 step_rows: int = 1 << 27, lookahead: int = 8, lookahead_rows: int = 1 << 30,
                  clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
-        if budget_bytes <= 0 or max_batch <= 0 or step_rows <= 0 or lookahead <= 0 or not 0.0 < scan_share <= 1.0:
-            raise ValueError("budget_bytes, max_batch, step_rows and lookahead must be positive, "
-                             "scan_share in (0, 1]")
+        if (budget_bytes <= 0 or max_batch <= 0 or step_rows <= 0 or lookahead <= 0 or lookahead_rows <= 0
+                or not 0.0 < scan_share <= 1.0):
+            raise ValueError("budget_bytes, max_batch, step_rows, lookahead and lookahead_rows must be "
+                             "positive, scan_share in (0, 1]")
         self.ex = executor
         self.budget = int(budget_bytes)
         self.scan_budget = max(1, int(budget_bytes * scan_share))
         self.max_batch = int(max_batch)
         self.step_rows = int(step_rows)
         self.lookahead = int(lookahead)
+        self.lookahead_rows = int(lookahead_rows)
         self.clock = clock
         self.sleep = sleep
         self.in_use = 0
@@ -132,7 +135,8 @@ class Server:
         nxt_arrival = 0
         waiting: collections.deque = collections.deque()
         scanning: List[_Active] = []          # admitted, predicates left, in admission order
-        steps: collections.deque = collections.deque()      # (seq, fence) of scan steps in flight
+        steps: collections.deque = collections.deque()      # (seq, fence, rows) of scan steps in flight
+        inflight_rows = 0
         counting: collections.deque = collections.deque()   # (seq, counts token, [_Active])
         blocked: collections.deque = collections.deque()    # (_Active, count): lookup waits for memory
         gathering: collections.deque = collections.deque()  # (seq, fence, [(a, count, extra, vals)])
@@ -157,15 +161,18 @@ class Server:
             enqueued = False
             # one scan step: the next predicate of the oldest scanning queries, one launch
             while steps and ex.is_done(steps[0][1]):
-                steps.popleft()
+                inflight_rows -= steps.popleft()[2]
+            batch, rows = [], 0
             if scanning and len(steps) < self.lookahead:
-                batch, rows = [], 0
                 for a in scanning:
                     n = ex.n_rows(a.q.table)
                     if batch and (len(batch) >= self.max_batch or rows + n > self.step_rows):
                         break
                     batch.append(a)
                     rows += n
+                if steps and inflight_rows + rows > self.lookahead_rows:
+                    batch = []
+            if batch:
                 items = []
                 for a in batch:
                     col, op, lo, hi = a.q.preds[a.k]
@@ -179,7 +186,8 @@ class Server:
                     a.k += 1
                     a.cur, a.nxt = a.nxt, a.cur
                 seq += 1
-                steps.append((seq, tok))
+                steps.append((seq, tok, rows))
+                inflight_rows += rows
                 fin = [a for a in batch if a.k >= len(a.q.preds)]
                 if fin:
                     scanning = [a for a in scanning if a.k < len(a.q.preds)]

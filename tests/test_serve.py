@@ -211,3 +211,67 @@ def test_poisson_and_summary():
 def test_query_without_predicate_rejected():
     with pytest.raises(ValueError):
         Server(HostExecutor(_tables()), budget_bytes=1 << 20).run([Query(0, "a", [], ["c0"])])
+
+
+class _Token:
+    def __init__(self, idx, value=None):
+        self.idx, self.value, self.done = idx, value, False
+
+
+class LazyExecutor(HostExecutor):
+    """Work completes only when the loop waits for it (in enqueue order), so
+    scan steps really are in flight between iterations."""
+
+    def __init__(self, tables):
+        super().__init__(tables)
+        self.tokens = []
+        self.max_scan_inflight = 0
+
+    def _token(self, value=None):
+        t = _Token(len(self.tokens), value)
+        self.tokens.append(t)
+        return t
+
+    def scan_step(self, items):
+        super().scan_step(items)
+        t = self._token()
+        t.scan = True
+        inflight = sum(1 for x in self.tokens if getattr(x, "scan", False) and not x.done)
+        self.max_scan_inflight = max(self.max_scan_inflight, inflight)
+        return t
+
+    def count_rows(self, pairs):
+        return self._token(super().count_rows(pairs))
+
+    def read_counts(self, handle):
+        assert handle.done
+        return handle.value
+
+    def fence(self):
+        return self._token()
+
+    def is_done(self, token):
+        return token.done
+
+    def wait(self, token):
+        for t in self.tokens[: token.idx + 1]:
+            t.done = True
+
+
+@pytest.mark.parametrize("lookahead,lookahead_rows,bound", [(8, 10_000, 2), (3, 1 << 30, 3), (8, 1, 1)])
+def test_scan_steps_in_flight_are_bounded(lookahead, lookahead_rows, bound):
+    # one scan per step (5000 rows each): at most `bound` steps in flight, by
+    # count or by rows, and one step always may go
+    tables = _tables()
+    qs = [q for q in _queries(tables, 30, seed=13) if q.table == "a"][:8]
+    for q in qs:
+        q.preds = (q.preds * 3)[:3]
+    ex = LazyExecutor(tables)
+    res = Server(ex, budget_bytes=1 << 30, max_batch=1, lookahead=lookahead, lookahead_rows=lookahead_rows).run(qs)
+    assert ex.max_scan_inflight == bound
+    for q in qs:
+        want, cnt = _plain(tables, q)
+        assert res[q.qid].count == cnt
+        for c in q.lookups:
+            assert np.array_equal(res[q.qid].values[c], want[c])
+
