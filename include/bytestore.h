@@ -329,9 +329,10 @@ enum {
     BST_TUNE_LOOKUP_GRID = 1,  /* workgroups of a lookup launch (0 = auto)             */
     BST_TUNE_BATCH_GRID = 2,   /* default workgroups of a batch launch (0 = auto)      */
     BST_TUNE_BATCH_GRAB = 3,   /* default tiles per grab of a batch launch             */
-    BST_TUNE_STAGE_PCT = 4,    /* a tile copies a later slice's run into LDS (one read)
-                                  instead of gathering group by group when at least
-                                  this percentage of its 64-row groups needs it       */
+    BST_TUNE_GATHER_ROWS = 4,  /* pending rows per 32-row lane (0..4, default 4) whose
+                                  later bytes a scan gathers one by one; a tile with
+                                  a lane holding more copies the level's run of the
+                                  slice into LDS with one read instead                */
     BST_TUNE_NKEYS = 5
 };
 int bst_tune_set(int key, int64_t value);

@@ -27,7 +27,7 @@ KMAX = 6
 TILE_ROWS = 2048
 NBUF = 19
 BUF_BS1, BUF_BS2, BUF_M2, BUF_DIR2, BUF_PACKED, BUF_DICT, BUF_TRIE = 0, 1, 6, 11, 16, 17, 18
-TUNE_SCAN_GRID, TUNE_LOOKUP_GRID, TUNE_BATCH_GRID, TUNE_BATCH_GRAB, TUNE_STAGE_PCT = 0, 1, 2, 3, 4
+TUNE_SCAN_GRID, TUNE_LOOKUP_GRID, TUNE_BATCH_GRID, TUNE_BATCH_GRAB, TUNE_GATHER_ROWS = 0, 1, 2, 3, 4
 
 
 class BstError(RuntimeError):

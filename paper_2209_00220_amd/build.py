@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libbytestore.so")
 SOURCES = [os.path.join(CSRC, f) for f in (
     "host_encode.cpp", "k_misc.hip", "k_scan_slices.hip", "k_scan_lt.hip", "k_scan_gt.hip", "k_scan_eq.hip",
     "k_scan_between.hip", "k_scan_packed_a.hip", "k_scan_packed_b.hip", "k_batch.hip", "k_batch_short.hip", "k_batch_packed.hip")]
-HEADERS = [os.path.join(CSRC, "internal.h"), os.path.join(CSRC, "device_common.h"), os.path.join(CSRC, "scan_kernel.h"),
+HEADERS = [os.path.join(CSRC, "internal.h"), os.path.join(CSRC, "device_common.h"), os.path.join(CSRC, "scan_kernel.h"), os.path.join(CSRC, "slice_scan.h"),
            os.path.join(CSRC, "batch_kernel.h"),
            os.path.join(ROOT, "include", "bytestore.h")]
 BUILD_DIR = os.path.join(ROOT, "_build")

@@ -2,7 +2,7 @@
 // the translation units that instantiate its variants.
 #pragma once
 
-#include "device_common.h"
+#include "slice_scan.h"
 
 namespace bst {
 namespace dev {

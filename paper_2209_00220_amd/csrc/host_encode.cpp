@@ -231,9 +231,11 @@ struct PpeBuilder {
 
 // ------------------------------------------------------------ layouts
 static inline uint64_t bs1_pos(uint64_t r) {
-    // tile-interleaved first slice: lane (r % 64) of a tile holds its 32 rows
-    // r = tile*2048 + k*64 + lane contiguously, k = 0..31
-    return (r & ~(uint64_t)(kTileRows - 1)) + ((r & 63) << 5) + ((r >> 6) & 31);
+    // tile-interleaved slice: lane L = (r / 32) % 64 of a tile owns its 32
+    // consecutive rows as eight dwords, row p = r % 32 in byte p / 8 of dword
+    // p % 8; dwords 0-3 of the lanes fill the tile's first 1 KB, dwords 4-7 its second
+    const uint64_t p = r & 31, lane = (r >> 5) & 63, i = p & 7;
+    return (r & ~(uint64_t)(kTileRows - 1)) + (i >> 2) * 1024 + lane * 16 + (i & 3) * 4 + (p >> 3);
 }
 
 static int log2_exact(uint32_t v) {
@@ -299,8 +301,8 @@ static void build_vbs(HostColumn& c, const uint32_t* rank, uint32_t T) {
     }
 }
 
-// ByteSlice: code left-aligned in K bytes; BS_1 tile-interleaved like PP-VBS,
-// BS_j (j >= 2) dense in row order.
+// ByteSlice: code left-aligned in K bytes; every slice tile-interleaved like
+// PP-VBS's BS_1.
 static void build_byteslice(HostColumn& c, const uint32_t* vals, uint32_t T) {
     const uint64_t n = c.n, npad = c.ntiles * kTileRows;
     const uint32_t K = c.K, w = c.width;
@@ -349,15 +351,10 @@ static uint32_t bits_for(uint64_t nd) {
     return w;
 }
 
-void choose_staging(const HostColumn& c, ScanLit* s, int pct) {
-    (void)c;
-    s->k2lo = 2 < s->llo ? ~0ull : 0ull;
-    s->k2hi = 2 < s->lhi ? ~0ull : 0ull;
-    s->k3lo = 3 < s->llo ? ~0ull : 0ull;
-    s->k3hi = 3 < s->lhi ? ~0ull : 0ull;
-    // a tile stages a level's run when at least `stage` of its 32 groups need
-    // that level (33: never)
-    s->stage = (pct <= 0 || pct > 100) ? 33u : std::max<uint32_t>(1u, (uint32_t)((32 * pct + 99) / 100));
+void choose_gather(ScanLit* s, int rows) {
+    // pending rows per 32-row lane that a level gathers straight from its slice;
+    // a tile with a lane holding more stages the level's run in LDS
+    s->gather = (uint32_t)std::max(0, std::min(rows, 4));
 }
 
 // Categorical PPE (Sec. 3.1, Algorithm 2): the distinct values, taken in

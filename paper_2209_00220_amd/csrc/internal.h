@@ -45,10 +45,9 @@ struct ScanLit {
     int32_t negate;      // result = valid & ~X instead of X
     uint64_t lo, hi;     // slice layouts: codes padded to BST_KMAX bytes; Bit-Packed: plain codes
     uint32_t llo, lhi;   // code lengths in bytes (slice layouts)
-    uint32_t stage;      // pending groups (of 32) at which a tile stages a level's run in LDS
+    uint32_t gather;     // pending rows per 32-row lane a level gathers directly (0..4);
+                         // a tile with a lane holding more stages the level's run in LDS
     uint32_t pad;
-    // all ones while byte j is shorter than the literal (j < l), for j = 2, 3
-    uint64_t k2lo, k2hi, k3lo, k3hi;
 };
 
 enum LitMode : int32_t {
@@ -62,10 +61,10 @@ enum LitMode : int32_t {
 
 // Rewrite a value predicate into code space for a column (host, exact).
 int rewrite_predicate(const HostColumn& c, const bst_pred& p, ScanLit* out);
-// Set the scan's staging threshold (ScanLit.stage) from `pct`: a tile copies a
-// level's run of BS_j into LDS, instead of gathering bytes group by group, when
-// at least pct % of its 32 groups still have rows pending at that level.
-void choose_staging(const HostColumn& c, ScanLit* s, int pct);
+// Set ScanLit.gather: a level gathers each pending row's byte straight from the
+// slice while no 32-row lane of the tile has more than `rows` (0..4) pending
+// rows, and otherwise copies the tile's run of BS_j into LDS with one read.
+void choose_gather(ScanLit* s, int rows);
 // Literal from explicit codes (op in code space).
 int code_literal(const HostColumn& c, int op, uint64_t lo, uint32_t llo, uint64_t hi, uint32_t lhi,
                  ScanLit* out);

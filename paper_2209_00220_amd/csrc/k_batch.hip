@@ -202,7 +202,7 @@ int bst_batch_prepare(const bst_column* const* cols, const bst_pred* preds, cons
         memset(&it, 0, sizeof(it));
         it.c = col->dev;
         it.lit = lit;
-        choose_staging(*col->host, &it.lit, (int)g_tune[BST_TUNE_STAGE_PCT]);
+        choose_gather(&it.lit, (int)g_tune[BST_TUNE_GATHER_ROWS]);
         it.pl = packed_literal(*col->host, lit);
         it.in_mask = in;
         it.out = outs[i];

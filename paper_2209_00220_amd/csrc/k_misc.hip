@@ -205,7 +205,7 @@ DeviceProps& props() {
     return p;
 }
 
-int64_t g_tune[BST_TUNE_NKEYS] = {0, 0, 0, 16, 30};
+int64_t g_tune[BST_TUNE_NKEYS] = {0, 0, 0, 16, 4};
 
 PackedLit packed_literal(const HostColumn& h, const ScanLit& s) {
     PackedLit p{0, 0, (uint32_t)s.negate, 0};
@@ -252,9 +252,9 @@ int run_scan(const bst_column* col, const ScanLit& lit, const uint64_t* in, uint
     if (c.n == 0) return BST_OK;
     if (lit.mode == kModeNone || lit.mode == kModeAll) return enqueue_fill(out, in, c.n, lit.mode == kModeAll ? 1 : 0, st);
     if (c.layout == BST_BITPACKED) return launch_packed(c, packed_literal(*col->host, lit), in, out, counters, st);
-    ScanLit staged = lit;
-    choose_staging(*col->host, &staged, (int)g_tune[BST_TUNE_STAGE_PCT]);
-    return launch_slices(c, staged, in, out, counters, st);
+    ScanLit tuned = lit;
+    choose_gather(&tuned, (int)g_tune[BST_TUNE_GATHER_ROWS]);
+    return launch_slices(c, tuned, in, out, counters, st);
 }
 
 uint32_t batch_kind(const bst_column* col, const ScanLit& lit) {
@@ -387,14 +387,14 @@ int bst_bv_compact(const uint64_t* bv, uint64_t n_rows, uint32_t* out_ids, uint6
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, (unsigned long long*)dev_count, 1);
         return hip_check(hipGetLastError(), "compact launch");
     }
-    hipLaunchKernelGGL(k_tile_popc, dim3(tile_grid(nt, 0)), dim3(kBlock), 0, st, bv, n_rows, counts, nt);
+    hipLaunchKernelGGL(k_tile_popc, dim3(tile_grid(nt, 0, 8)), dim3(kBlock), 0, st, bv, n_rows, counts, nt);
     const uint64_t nb = (nt + kScanBlock - 1) / kScanBlock;   // at most 2 * kScanBlock (n < 2^32)
     uint64_t* bsum = offsets + nt + 1;
     hipLaunchKernelGGL(k_block_sums, dim3((uint32_t)nb), dim3(kScanBlock), 0, st, counts, nt, bsum);
     hipLaunchKernelGGL(k_scan_block_sums, dim3(1), dim3(kScanBlock), 0, st, bsum, (uint32_t)nb);
     hipLaunchKernelGGL(k_scan_offsets, dim3((uint32_t)nb), dim3(kScanBlock), 0, st, counts, nt, bsum, offsets,
                        (unsigned long long*)dev_count);
-    hipLaunchKernelGGL(k_write_ids, dim3(tile_grid(nt, 0)), dim3(kBlock), 0, st, bv, n_rows, offsets, nt, out_ids, cap,
+    hipLaunchKernelGGL(k_write_ids, dim3(tile_grid(nt, 0, 8)), dim3(kBlock), 0, st, bv, n_rows, offsets, nt, out_ids, cap,
                        dev_status);
     return hip_check(hipGetLastError(), "compact launch");
 }

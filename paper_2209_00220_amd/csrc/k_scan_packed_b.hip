@@ -31,7 +31,7 @@ static void launch_packed_w(uint32_t grid, hipStream_t st, const DevCol& c, cons
 
 int launch_packed_17_32(const DevCol& c, const PackedLit& pl, const uint64_t* in, uint64_t* out,
                       unsigned long long* counters, hipStream_t st) {
-    const uint32_t grid = tile_grid(c.ntiles, g_tune[BST_TUNE_SCAN_GRID]);
+    const uint32_t grid = tile_grid(c.ntiles, g_tune[BST_TUNE_SCAN_GRID], 2);
     switch (c.width) {
 #define BST_LW(W) \
     case W: launch_packed_w<W>(grid, st, c, pl, in, out, counters); break;

@@ -1,24 +1,26 @@
 // Single-column scans of the slice layouts (PP-VBS, ByteSlice): one wave per
-// 2048-row tile, grid-stride over tiles, the next two tiles' loads in flight.
+// 2048-row tile, grid-stride over tiles, the next tiles' loads in flight.
 #pragma once
 
-#include "device_common.h"
+#include "slice_scan.h"
 
 namespace bst {
 namespace dev {
 
-// Waves per SIMD the variant is built for: 8 (at most 64 VGPRs, a few spilled)
-// hides more of the later levels' gather latency than fewer waves do (PP-VBS
-// '<' with a multi-byte literal keeps two tiles in flight instead of three to
-// fit), except for PP-VBS BETWEEN, whose two literals need more registers: it
-// was fastest built for 6 (77 VGPRs, three tiles in flight), ahead of 7 and 8.
-template <int MODE, bool DENSE>
+// Waves per SIMD the variant is built for: 8 (64 VGPRs) where a tile's work
+// ends with its byte-1 pass; variants that keep a tile's later-byte reads in
+// flight (two tiles' gathered bytes or dense slice bytes besides two tiles'
+// loads), and BETWEEN with its two literals, are built for 7 (73 VGPRs);
+// ByteSlice BETWEEN with a multi-byte literal, whose tile state holds a lane's
+// 32 bytes of the second slice, for 6 (85 VGPRs).
+template <int MODE, int SHORT, bool DENSE>
 constexpr int scan_waves() {
-    return (MODE == kModeBetween && !DENSE) ? kMinWaves : 8;
+    constexpr bool one = SliceScan<MODE, SHORT, DENSE, false, false>::kByte1Only;
+    return (one && MODE != kModeBetween) ? 8 : (DENSE && MODE == kModeBetween && !one) ? 6 : 7;
 }
 
 template <int MODE, int SHORT, bool DENSE, bool HAS_IN, bool COUNT>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(scan_waves<MODE, DENSE>(), 8))) void k_scan_slices(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(scan_waves<MODE, SHORT, DENSE>(), 8))) void k_scan_slices(
     const DevCol c, const ScanLit lit, const uint64_t* __restrict__ in_mask, uint64_t* __restrict__ out,
     unsigned long long* __restrict__ counters) {
     __shared__ __attribute__((aligned(16))) uint8_t stage[kWavesPerBlock][kWaveLds];

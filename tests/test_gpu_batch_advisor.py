@@ -57,22 +57,32 @@ def test_batch_equals_single(use_graph):
             dc = cols[ci][lay][1]
             outs.append(dc.new_bv())
             specs.append((dc, op, a, b if op == "between" else None, None))
-        # one item pipelines another's result
-        specs[5] = (specs[5][0], specs[5][1], specs[5][2], specs[5][3], None)
+        # predicate pipelining across batches: item 5 takes as its incoming mask
+        # the result of a scan on the same column that an earlier batch wrote
+        ci5, lay5, op5, a5, b5 = items[5]
+        x5, _ = xs[ci5]
+        first_lit = int(np.median(x5))
+        first_out = cols[ci5]["bitpacked"][1].new_bv()
+        first = Batch([(cols[ci5]["bitpacked"][1], "ge", first_lit, None, None)], [first_out])
+        specs[5] = (specs[5][0], op5, a5, b5 if op5 == "between" else None, first_out)
         batch = Batch(specs, outs)
         for rep in range(3):
             for o in outs:
                 o.fill_(-1)
+            first_out.fill_(0)
+            first.launch(grid=0, tiles_per_grab=1, use_graph=use_graph)
             batch.launch(grid=0, tiles_per_grab=2, use_graph=use_graph)
             torch.cuda.synchronize()
-            for (ci, lay, op, a, b), o in zip(items, outs):
+            for k, ((ci, lay, op, a, b), o) in enumerate(zip(items, outs)):
                 x, w = xs[ci]
-                want = scan_values_bv(x, op, a, b if op == "between" else None)
-                assert np.array_equal(bv_to_numpy(o), want), (rep, lay, op, a, b)
+                prior = (x >= np.uint32(first_lit)) if k == 5 else None
+                want = scan_values_bv(x, op, a, b if op == "between" else None, prior)
+                assert np.array_equal(bv_to_numpy(o), want), (rep, k, lay, op, a, b)
             # eager work between graph replays
             _ = cols[0]["ppvbs"][1].scan("lt", 5)
             torch.cuda.synchronize()
         batch.close()
+        first.close()
     finally:
         for c in cols:
             close_columns(c)

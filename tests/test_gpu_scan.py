@@ -214,21 +214,21 @@ def test_repeatable():
         close_columns(cols)
 
 
-@pytest.mark.parametrize("grid,stage_pct", [(1, 0), (3, 1), (3, 100)])
-def test_scan_parity_many_tiles_per_wave(grid, stage_pct):
+@pytest.mark.parametrize("grid,gather", [(1, 0), (3, 1), (3, 4), (1, 2)])
+def test_scan_parity_many_tiles_per_wave(grid, gather):
     """A tiny launch (grid workgroups of 4 waves) gives each wave from two to
     nine tiles, odd and even counts, so every prefetch slot of the tile
-    rotation holds a tile at some point and the slots past a wave's last tile
-    are exercised; the staging threshold switches later levels between the
-    staged run (1 %: any pending group) and group gathers (0: never staged;
-    100 %: only when every group is pending)."""
+    rotation and of the deferred level-2 reads holds a tile at some point and
+    the slots past a wave's last tile are exercised; the gather limit switches
+    later levels between the run staged in LDS (0: whenever a row is pending)
+    and per-row gathers (up to 1, 2 or 4 pending rows per lane)."""
     from paper_2209_00220_amd import _lib as L
     from paper_2209_00220_amd.column import bv_from_numpy
 
-    flush("scan parity with grid=%d stage_pct=%d" % (grid, stage_pct))
-    saved = (L.bst_tune_get(L.TUNE_SCAN_GRID), L.bst_tune_get(L.TUNE_STAGE_PCT))
+    flush("scan parity with grid=%d gather=%d" % (grid, gather))
+    saved = (L.bst_tune_get(L.TUNE_SCAN_GRID), L.bst_tune_get(L.TUNE_GATHER_ROWS))
     L.bst_tune_set(L.TUNE_SCAN_GRID, grid)
-    L.bst_tune_set(L.TUNE_STAGE_PCT, stage_pct)
+    L.bst_tune_set(L.TUNE_GATHER_ROWS, gather)
     try:
         for n, w, s in ((2048 * 9 + 5, 20, 1.0), (2048 * 14, 16, 0.5), (70_001, 24, 1.2)):
             x = datagen.zipf_column(n, w, s, seed=3 * n + w)
@@ -251,4 +251,4 @@ def test_scan_parity_many_tiles_per_wave(grid, stage_pct):
                 close_columns(cols)
     finally:
         L.bst_tune_set(L.TUNE_SCAN_GRID, saved[0])
-        L.bst_tune_set(L.TUNE_STAGE_PCT, saved[1])
+        L.bst_tune_set(L.TUNE_GATHER_ROWS, saved[1])

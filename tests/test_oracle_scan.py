@@ -7,7 +7,7 @@ from oracle.dictionary import build_dictionary, rank_bits
 from oracle.layout import bitpacked_build, byteslice_build, pack_bits, unpack_bits, vbs_build
 from oracle.ppe import padded, ppe_numerical
 from oracle.scan import (
-    OPS, CodeTable, classify, classify_rows, scan_bitpacked, scan_byteslice, scan_values,
+    OPS, CodeTable, classify, classify_rows, scan_bitpacked, scan_byteslice, scan_padded_codes, scan_values,
     scan_vbs, select_by_sign,
 )
 
@@ -107,3 +107,37 @@ def test_scan_values_definitions():
     assert list(scan_values(x, "between", 5, 7)) == [0, 1, 1, 1, 0]
     assert list(scan_values(x, "between", 7, 5)) == [0, 0, 0, 0, 0]
     assert list(scan_values(x, "gt", 0, in_mask=[1, 1, 0, 1, 0])) == [0, 1, 0, 1, 0]
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_select_by_sign_every_operator(seed):
+    """Each operator's selection from the byte-serial signs (the classifier of
+    Sec. 3.3) equals the comparison of the zero-padded codes as plain integers
+    (Sec. 3.1's order), for one and two literals, present and absent: a wrong
+    branch (say '<=' taken as '<', or BETWEEN's bounds swapped) fails here."""
+    x = datagen.zipf_column(30_000, 16, 1.0, seed=seed, mapping=datagen.SORTED if seed == 4 else datagen.SCATTER)
+    A, Q, rank = build_dictionary(x)
+    C, L = ppe_numerical(Q)
+    K = int(L.max())
+    P = padded(C, L, K)
+    Cr, Lr, Pr = C[rank], L[rank], P[rank]
+    rng = np.random.default_rng(seed)
+    ks = list(rng.integers(0, A.shape[0], size=12)) + [0, A.shape[0] - 1]
+    for k in ks:
+        s_lo, _ = classify_rows(Cr, Lr, int(C[k]), int(L[k]))
+        k2 = int(rng.integers(0, A.shape[0]))
+        s_hi, _ = classify_rows(Cr, Lr, int(C[k2]), int(L[k2]))
+        for op in OPS:
+            got = select_by_sign(op, s_lo, s_hi if op == "between" else None)
+            want = scan_padded_codes(Pr, op, int(P[k]), int(P[k2]) if op == "between" else None)
+            assert np.array_equal(got, want), (op, k, k2)
+    # literals that are not codes of the column: a proper prefix of a stored
+    # code, and a code past the last one
+    long = int(np.argmax(L))
+    if L[long] >= 2:
+        c1, l1 = int(C[long]) >> 8 * (int(L[long]) - 1), 1
+        s, _ = classify_rows(Cr, Lr, c1, l1)
+        for op in OPS[:-1]:
+            assert np.array_equal(select_by_sign(op, s), scan_padded_codes(Pr, op, int(padded([c1], [l1], K)[0])))
+    with pytest.raises(ValueError):
+        select_by_sign("like", s_lo)
