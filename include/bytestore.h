@@ -251,6 +251,23 @@ int bst_lookup_bv(const bst_column* col, const uint64_t* bv, uint32_t* out_value
                   uint64_t* dev_count, uint32_t* ids_tmp, void* workspace, uint32_t* dev_status,
                   void* stream);
 
+/*
+ * bst_lookup_bv without caller-provided device memory, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, hosts that forbid
+ * allocation): the compaction workspace and the row-ID staging live in a device
+ * array the library holds per GPU (12.6 MB, reserved on that GPU until the
+ * process ends).  The caller passes only inputs and outputs, as for
+ * bst_lookup_bv.  Limits: columns of at most bst_lookup_bv_static_max_rows()
+ * rows (2^29) and cap at most bst_lookup_bv_static_max_ids() (2^21); larger
+ * ones return BST_ERANGE.  The array belongs to the current device, and every
+ * call on one GPU shares it: calls whose work overlaps on one GPU (other
+ * streams, other host threads) race and must be ordered by the caller.
+ */
+int bst_lookup_bv_static(const bst_column* col, const uint64_t* bv, uint32_t* out_values, uint64_t cap,
+                         uint64_t* dev_count, uint32_t* dev_status, void* stream);
+uint64_t bst_lookup_bv_static_max_rows(void);
+uint64_t bst_lookup_bv_static_max_ids(void);
+
 /* ---- bitvector helpers (Sec. 2.2: conjunctions and disjunctions of scan
  * results are bitwise operations on their bitvectors) ----------------------
  * All take ceil(n_rows/64) device words per vector, write `out` (which may

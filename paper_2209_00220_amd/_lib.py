@@ -79,6 +79,9 @@ _PROTOS = {
     "bst_compact_workspace_bytes": (_U64, [_U64]),
     "bst_bv_compact": (_I, [_P, _U64, _P, _U64, _P, _P, _P, _P]),
     "bst_lookup_bv": (_I, [_P, _P, _P, _U64, _P, _P, _P, _P, _P]),
+    "bst_lookup_bv_static": (_I, [_P, _P, _P, _U64, _P, _P, _P]),
+    "bst_lookup_bv_static_max_rows": (_U64, []),
+    "bst_lookup_bv_static_max_ids": (_U64, []),
     "bst_bv_and": (_I, [_P, _P, _P, _U64, _P]),
     "bst_bv_or": (_I, [_P, _P, _P, _U64, _P]),
     "bst_bv_andnot": (_I, [_P, _P, _P, _U64, _P]),
@@ -262,6 +265,18 @@ def bst_bv_compact(bv, n_rows, out_ids, cap, dev_count, workspace, dev_status, s
 def bst_lookup_bv(col, bv, out_values, cap, dev_count, ids_tmp, workspace, dev_status, stream):
     _call("bst_lookup_bv", col, _ptr(bv), _ptr(out_values), cap, _ptr(dev_count), _ptr(ids_tmp),
           _ptr(workspace), _ptr(dev_status), stream)
+
+
+def bst_lookup_bv_static(col, bv, out_values, cap, dev_count, dev_status, stream):
+    _call("bst_lookup_bv_static", col, _ptr(bv), _ptr(out_values), cap, _ptr(dev_count), _ptr(dev_status), stream)
+
+
+def bst_lookup_bv_static_max_rows():
+    return int(lib().bst_lookup_bv_static_max_rows())
+
+
+def bst_lookup_bv_static_max_ids():
+    return int(lib().bst_lookup_bv_static_max_ids())
 
 
 def bst_bv_and(a, b, out, n_rows, stream):

@@ -413,6 +413,78 @@ int bst_lookup_bv(const bst_column* col, const uint64_t* bv, uint32_t* out_value
     return hip_check(hipGetLastError(), "lookup launch");
 }
 
+}  // extern "C"
+
+// ---- lookup of qualifying rows without caller-provided device memory ----
+// The compaction workspace and the row-ID staging of bst_lookup_bv live in one
+// file-scope device array.  Host code never passes `scratch` itself to a kernel
+// or copy: there the name is a host-side stand-in, not the device address.  The
+// address is taken per device with hipGetSymbolAddress (each GPU holds its own
+// copy) and kept for the process.
+namespace {
+constexpr uint64_t kStaticMaxRows = 1ull << 29;   // rows of the scanned column
+constexpr uint64_t kStaticMaxIds = 1ull << 21;    // selected rows looked up per call
+constexpr uint64_t kStaticTiles = kStaticMaxRows / kTileRows;
+constexpr uint64_t kStaticCompactBytes =
+    8 * (2 * kStaticTiles + 2 + (kStaticTiles + kScanBlock - 1) / kScanBlock);   // bst_compact_workspace_bytes
+constexpr uint64_t kStaticIdsOffset = (kStaticCompactBytes + 255) / 256 * 256;
+constexpr uint64_t kScratchBytes = kStaticIdsOffset + 4 * kStaticMaxIds;   // 12.6 MB
+constexpr int kMaxDevices = 64;
+
+struct StaticScratch {
+    std::mutex mu;
+    void* ptr[kMaxDevices] = {};
+};
+StaticScratch& static_scratch() {
+    static StaticScratch* s = new StaticScratch;   // never destroyed
+    return *s;
+}
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+// Device address of the current device's scratch array, taken on the first call
+// on that device.
+static int scratch_address(void** out) {
+    int dev = 0;
+    int rc = hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (rc) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return set_error(BST_EUNSUPPORTED, "device index beyond the scratch table");
+    StaticScratch& s = static_scratch();
+    std::lock_guard<std::mutex> lock(s.mu);
+    if (!s.ptr[dev]) {
+        void* p = nullptr;
+        rc = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (rc) return rc;
+        if (!p) return set_error(BST_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        s.ptr[dev] = p;
+    }
+    *out = s.ptr[dev];
+    return BST_OK;
+}
+
+extern "C" {
+
+uint64_t bst_lookup_bv_static_max_rows(void) { return kStaticMaxRows; }
+uint64_t bst_lookup_bv_static_max_ids(void) { return kStaticMaxIds; }
+
+int bst_lookup_bv_static(const bst_column* col, const uint64_t* bv, uint32_t* out_values, uint64_t cap,
+                         uint64_t* dev_count, uint32_t* dev_status, void* stream) {
+    if (!col) return set_error(BST_EINVAL, "NULL column");
+    if (col->dev.n > kStaticMaxRows)
+        return set_error(BST_ERANGE, "bst_lookup_bv_static takes columns of at most 2^29 rows; use bst_lookup_bv");
+    if (cap > kStaticMaxIds)
+        return set_error(BST_ERANGE, "bst_lookup_bv_static looks up at most 2^21 rows per call; use bst_lookup_bv");
+    void* base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc) return rc;
+    // every scratch location a kernel reads is written earlier in the same
+    // call, so nothing needs clearing between calls
+    uint8_t* sp = static_cast<uint8_t*>(base);
+    return bst_lookup_bv(col, bv, out_values, cap, dev_count, reinterpret_cast<uint32_t*>(sp + kStaticIdsOffset), sp,
+                         dev_status, stream);
+}
+
 int bst_bv_and(const uint64_t* a, const uint64_t* b, uint64_t* out, uint64_t n_rows, void* stream) {
     if (n_rows == 0) return BST_OK;
     if (!a || !b || !out) return set_error(BST_EINVAL, "NULL argument");
