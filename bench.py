@@ -38,8 +38,13 @@ if ROOT not in sys.path:
 METRIC = "scan Gtuples/s + % HBM peak (PP-VBS vs ByteSlice); lookup Mrows/s; p99"
 HBM_PEAK_GBS = 8000.0
 LAYOUTS = ("ppvbs", "byteslice", "bitpacked")
-KERNEL_SOURCES = ("paper_2209_00220_amd/csrc/device_common.h", "paper_2209_00220_amd/csrc/scan_kernel.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ppvbs_scan_500M_traffic.txt")
+KERNEL_SOURCES = ("paper_2209_00220_amd/csrc/device_common.h", "paper_2209_00220_amd/csrc/slice_scan.h",
+                  "paper_2209_00220_amd/csrc/scan_kernel.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_lookup_500M_traffic.txt")
+TRACE_CMD = "rocprofv3 --kernel-trace --stats -d gpurun_out/trace -o run --output-format csv -- python3 bench.py"
+PMC_CMDS = ["rocprofv3 --pmc %s -d gpurun_out/%s -o run --output-format csv -- python3 bench.py --steps 1 "
+            "--warmup 0 --no-batch --serve-queries 0 --no-cpu-baseline --copy-calibration" % (c, d)
+            for c, d in (("FETCH_SIZE", "pmc_fetch"), ("WRITE_SIZE", "pmc_write"))]
 
 
 def progress(msg: str):
@@ -65,9 +70,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per PP-VBS scan launch from the committed rocprofv3 counter summary,
-    only when it was taken on the current kernel source."""
+def read_traffic(key: str = "hbm_bytes_per_launch"):
+    """HBM bytes per PP-VBS launch (key: scan, or lookup_hbm_bytes_per_launch) from
+    the committed rocprofv3 counter summary, only when it was taken on the current
+    kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -78,37 +84,299 @@ def read_traffic():
     if kv.get("kernel_hash") != kernel_hash():
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[key])
     except (KeyError, ValueError):
         return None
 
 
-def cpu_baseline(x, preds, sample_rows: int):
-    """The oracle (decode every code, compare, pack bits) on the first sample_rows rows."""
+LINE_BYTES = 128   # a random access fills one L2 line of 128 bytes on this chip
+
+
+def lookup_alg_bytes_per_id(info) -> float:
+    """Algorithmic bytes of one lookup by row ID: the 4-byte ID and 4-byte value,
+    plus one 128-byte line per random access the layout needs.  PP-VBS: BS_1;
+    then, per later byte j <= L(r), the M_j word, the directory entry and the
+    BS_j byte; and the M_{L+1} word that shows the code ends (when L < K).
+    ByteSlice: one line per slice.  Bit-Packed: one line, two when the code
+    straddles two dwords.  Decode tables (trie, dictionary) are not counted."""
+    K = int(info.k_max)
+    if info.layout == 2:   # PP-VBS
+        n = float(info.n_rows) or 1.0
+        lines = 0.0
+        for L in range(1, K + 1):
+            f = info.rows_by_len[L] / n
+            lines += f * (1 + 3 * (L - 1) + (1 if L < K else 0))
+    elif info.layout == 1:
+        lines = float(K)
+    else:
+        w = int(info.width_bits)
+        lines = 1.0 + sum(1 for k in range(32) if (k * w) % 32 + w > 32) / 32.0
+    return 8.0 + LINE_BYTES * lines
+
+
+# ---------------------------------------------------------------- profile summaries
+# The committed files under profiles/ are made from rocprofv3's CSV output by the
+# two functions below (CPU only): the commands that produced the CSVs and the
+# command that summarised them are written into each file's header.
+STEP_KERNELS = ("k_scan_slices", "k_scan_packed", "k_lookup", "k_fill")
+
+
+def _kernel_rows(path):
+    import csv
+
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _short(name: str) -> str:
+    return name.replace("void ", "").replace("bst::dev::", "").split("(")[0]
+
+
+def _is_step_kernel(name: str) -> bool:
+    s = _short(name)
+    if not any(s.startswith(k) for k in STEP_KERNELS):
+        return False
+    return not (s.startswith("k_scan_slices") and s.rstrip(">").endswith("true"))   # instrumented counters run
+
+
+def _step_launches(rows):
+    """The launches of the benchmark steps, in order: scans and lookups, without the
+    instrumented counter runs before them (Bit-Packed's counter runs use the plain
+    kernel, so the sequence starts at the first step's first slice-layout scan)."""
+    seq = [r for r in rows if _is_step_kernel(r["Kernel_Name"])]
+    k = 0
+    while k < len(seq) and not _short(seq[k]["Kernel_Name"]).startswith("k_scan_slices"):
+        k += 1
+    return seq[k:]
+
+
+def _step_layout_order(n_preds: int, layouts):
+    """(layout, predicate index or 'lookup') of each launch of one benchmark step."""
+    order = []
+    for lay in layouts:
+        order += [(lay, i) for i in range(n_preds)] + [(lay, "lookup")]
+    return order
+
+
+def summarize_trace(trace_dir: str, steps: int, warmup: int, cmd: str, out_path: str, preds, layouts=LAYOUTS):
+    """Per-launch durations of the timed steps from a rocprofv3 --kernel-trace run of
+    the default benchmark, plus the --stats table of the whole run."""
+    import numpy as np
+
+    rows = _kernel_rows(os.path.join(trace_dir, "run_kernel_trace.csv"))
+    seq = _step_launches(rows)
+    order = _step_layout_order(len(preds), layouts)
+    per = len(order)
+    timed = seq[warmup * per:(warmup + steps) * per]
+    assert len(timed) == steps * per, "trace holds %d step launches, expected %d" % (len(timed), steps * per)
+    dur = {}
+    names = {}
+    for k, r in enumerate(timed):
+        key = order[k % per]
+        dur.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        names[key] = _short(r["Kernel_Name"])
+    lines = ["rocprofv3 kernel trace of the default benchmark: 500M-row column, 20-bit Zipf(1.0) values,",
+             "%d predicates x %d layouts + a 5M-ID lookup per layout per step; %d warmup and %d timed steps," % (
+                 len(preds), len(layouts), warmup, steps),
+             "then the batched launch and the serving run (their kernels appear in the stats table only).",
+             "",
+             "commands (repo root; TMPDIR=/tmp):",
+             "  " + cmd,
+             "  python3 bench.py --summarize-trace gpurun_out/trace --out profiles/scan_lookup_500M_kernel_trace.txt",
+             "",
+             "timed steps only (per launch, from the trace's start/end stamps, microseconds):",
+             "  %-12s %6s %10s %10s %10s" % ("group", "calls", "avg_us", "min_us", "max_us")]
+    for lay in layouts:
+        for what in ("scan", "lookup"):
+            v = [x for key, xs in dur.items() if key[0] == lay and ((key[1] == "lookup") == (what == "lookup"))
+                 for x in xs]
+            lines.append("  %-12s %6d %10.1f %10.1f %10.1f" % (lay + " " + what, len(v), np.mean(v), min(v), max(v)))
+    lines += ["", "scan launches of the timed steps by predicate (average over steps, microseconds):"]
+    for lay in layouts:
+        for i, (op, lo, hi, sel) in enumerate(preds):
+            lit = "%d..%d" % (lo, hi) if hi is not None else "%d" % lo
+            lines.append("  %-9s %-8s %-16s sel %.4f  %-45s %7.1f" % (lay, op, lit, sel, names[(lay, i)],
+                                                                     np.mean(dur[(lay, i)])))
+    stats = _kernel_rows(os.path.join(trace_dir, "run_kernel_stats.csv"))
+    lines += ["", "--stats of the whole run (top 25 by total time):",
+              "  %-70s %6s %12s %10s" % ("kernel", "calls", "total_ms", "avg_us")]
+    for r in stats[:25]:
+        lines.append("  %-70s %6s %12.3f %10.1f" % (_short(r["Name"])[:70], r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+                                                    float(r["AverageNs"]) / 1e3))
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def summarize_counters(fetch_dir: str, write_dir: str, cmds, out_path: str, preds, layouts=LAYOUTS):
+    """HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
+    WRITE_SIZE, in KiB per dispatch) of a one-step benchmark, each scaled by what
+    the same counter reads for a 1 GiB device-to-device copy at the start."""
+    import numpy as np
+
+    def load(d, counter):
+        rows = _kernel_rows(os.path.join(d, "run_counter_collection.csv"))
+        rows = [r for r in rows if r["Counter_Name"] == counter]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return rows
+
+    fr, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy_f = [r for r in fr if "copyBuffer" in r["Kernel_Name"]][0]
+    copy_w = [r for r in wr if "copyBuffer" in r["Kernel_Name"]][0]
+    gib = float(1 << 30)
+    f_scale = gib / (float(copy_f["Counter_Value"]) * 1024)   # the copy reads 1 GiB
+    w_scale = gib / (float(copy_w["Counter_Value"]) * 1024)   # and writes 1 GiB
+    fs, ws = _step_launches(fr), _step_launches(wr)
+    order = _step_layout_order(len(preds), layouts)
+    assert len(fs) == len(ws) == len(order), (len(fs), len(ws), len(order))
+    lines = ["HBM traffic per launch of the benchmark step (500M-row column, 20-bit Zipf(1.0)), from",
+             "two rocprofv3 counter runs of a one-step benchmark; kernel_hash names the scan kernel",
+             "sources these counters were taken on (bench.py reports roofline.traffic only when it",
+             "matches the current sources).",
+             "",
+             "commands (repo root; TMPDIR=/tmp):"] + ["  " + c for c in cmds] + [
+             "  python3 bench.py --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write --out profiles/scan_lookup_500M_traffic.txt",
+             "",
+             "calibration: the 1 GiB device-to-device copy reads FETCH_SIZE = %.1f KiB and writes WRITE_SIZE = %.1f KiB;"
+             % (float(copy_f["Counter_Value"]), float(copy_w["Counter_Value"])),
+             "fetch is scaled x%.3f and write x%.3f below." % (f_scale, w_scale), ""]
+    per_lay = {}
+    for (lay, i), a, b in zip(order, fs, ws):
+        assert a["Kernel_Name"] == b["Kernel_Name"]
+        fb = float(a["Counter_Value"]) * 1024 * f_scale
+        wb = float(b["Counter_Value"]) * 1024 * w_scale
+        per_lay.setdefault(lay, []).append((i, _short(a["Kernel_Name"]), fb, wb))
+    for lay in layouts:
+        lines.append("%s launches (fetch and write MB per launch, scaled):" % lay)
+        scans = []
+        for i, name, fb, wb in per_lay[lay]:
+            if i == "lookup":
+                lines.append("  %-8s %-16s %-45s fetch %8.1f  write %6.1f" % ("lookup", "5M ids", name, fb / 1e6, wb / 1e6))
+                continue
+            op, lo, hi, _ = preds[i]
+            lit = "%d..%d" % (lo, hi) if hi is not None else "%d" % lo
+            lines.append("  %-8s %-16s %-45s fetch %8.1f  write %6.1f" % (op, lit, name, fb / 1e6, wb / 1e6))
+            scans.append(fb + wb)
+        lines.append("  average HBM bytes per scan launch: %.0f" % np.mean(scans))
+        lines.append("")
+    pp = [fb + wb for i, _, fb, wb in per_lay.get("ppvbs", []) if i != "lookup"]
+    lk = [fb + wb for i, _, fb, wb in per_lay.get("ppvbs", []) if i == "lookup"]
+    lines += ["kernel_hash: %s" % kernel_hash(),
+              "hbm_bytes_per_launch: %.0f" % np.mean(pp),
+              "lookup_hbm_bytes_per_launch: %.0f" % (lk[0] if lk else float("nan"))]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_threads() -> int:
+    """Worker threads for the CPU baseline: the host cores this process may use,
+    at most 16 (a one-GPU share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_chunks(x, threads: int):
+    """The oracle's own PP-VBS layout of x (dictionary, Algorithm 1, VBS), split into
+    `threads` chunks of whole 64-row groups; each chunk's starting cursor into
+    every BS_j comes from one popcount pass over M_j."""
     import numpy as np
 
     from oracle.dictionary import build_dictionary
     from oracle.layout import vbs_build
     from oracle.ppe import ppe_numerical
-    from oracle.scan import CodeTable, scan_vbs
+    from oracle.scan import CodeTable
 
-    xs = np.ascontiguousarray(x[:sample_rows])
-    A, Q, rank = build_dictionary(xs)
+    A, Q, rank = build_dictionary(x)
     C, Lc = ppe_numerical(Q)
     K = int(Lc.max())
     BS, M = vbs_build(C[rank], Lc[rank], K)
     table = CodeTable(A, C, Lc, K)
-    t0 = time.perf_counter()
-    for op, lo, hi, _ in preds:
-        scan_vbs(BS, M, K, table, op, lo, hi)
-    dt = time.perf_counter() - t0
+    n = x.shape[0]
+    bounds = sorted(set([min(n, (n * k // threads + 63) // 64 * 64) for k in range(threads)] + [n]))
+    cur = {j: np.concatenate([[0], np.cumsum(M[j], dtype=np.int64)])[bounds] for j in range(2, K + 1)}
+    chunks = []
+    for k in range(len(bounds) - 1):
+        r0, r1 = bounds[k], bounds[k + 1]
+        bs = [None, BS[1][r0:r1]] + [BS[j][cur[j][k]:cur[j][k + 1]] for j in range(2, K + 1)]
+        m = [None, None] + [M[j][r0:r1] for j in range(2, K + 1)]
+        chunks.append((r0, bs, m))
+    return chunks, K, table
+
+
+def _time_oracle(chunks, K, table, preds, ids, threads: int):
+    """Seconds for every scan of `preds` and for the lookup of `ids`, the chunks
+    spread over `threads` host threads (numpy releases the interpreter lock in its
+    array operations)."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    from oracle.lookup import lookup_ids
+    from oracle.scan import decode_vbs_values, scan_vbs
+
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        t0 = time.perf_counter()
+        for op, lo, hi, _ in preds:
+            list(ex.map(lambda ch: scan_vbs(ch[1], ch[2], K, table, op, lo, hi), chunks))
+        t_scan = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        vals = list(ex.map(lambda ch: decode_vbs_values(ch[1], ch[2], K, table), chunks))
+        lookup_ids(np.concatenate(vals), ids)
+        t_lookup = time.perf_counter() - t0
+    return t_scan, t_lookup
+
+
+def cpu_baseline(x, preds, ids, sample_rows: int, threads: int):
+    """The oracle (decode every code, compare, pack bits; lookups index the decoded
+    values) timed on the host: every benchmark predicate on the first sample_rows
+    rows of the column, and the benchmark's row IDs that fall in that range, at
+    `threads` host threads and at one; then the small single-column workload
+    (1M rows, one '<' scan, 10k lookups) in full."""
+    import numpy as np
+
+    from datagen import workloads
+
+    xs = np.ascontiguousarray(x[:sample_rows])
+    sid = ids[ids < sample_rows]
+    chunks, K, table = _oracle_chunks(xs, threads)
+    ts_t, tl_t = _time_oracle(chunks, K, table, preds, sid, threads)
+    ts_1, tl_1 = _time_oracle(chunks, K, table, preds, sid, 1)
+    c1 = workloads.config1()
+    x1 = c1["x"]
+    ch1, K1, tb1 = _oracle_chunks(x1, threads)
+    p1 = [("lt", c1["lt_literal"], None, c1["lt_selectivity"])]
+    c1_t = _time_oracle(ch1, K1, tb1, p1, c1["ids"], threads)
+    c1_1 = _time_oracle(ch1, K1, tb1, p1, c1["ids"], 1)
+    rate = lambda rows, t: round(rows / t / 1e9, 6)
     return {
-        "value": round(sample_rows * len(preds) / dt / 1e9, 6),
+        "value": rate(sample_rows * len(preds), ts_t),
         "unit": "Gtuples/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": "PP-VBS scans (decode, compare, pack) of the first %d rows of the same column, "
-                  "the same %d predicates, numpy on one host thread, %.1f s" % (sample_rows, len(preds), dt),
+        "sample": "PP-VBS scans (decode, compare, pack) of the first %d rows of the same column, all %d "
+                  "predicates, %d host threads (%.1f s; one thread %.1f s); lookups of the %d benchmark row IDs "
+                  "in that range (decode and index)" % (sample_rows, len(preds), threads, ts_t, ts_1, sid.shape[0]),
+        "value_1thread": rate(sample_rows * len(preds), ts_1),
+        "lookup_mrows": round(sid.shape[0] / tl_t / 1e6, 3),
+        "lookup_mrows_1thread": round(sid.shape[0] / tl_1 / 1e6, 3),
+        "cpu_model": _cpu_model(),
+        "small_workload": {
+            "rows": int(x1.shape[0]), "scan_gtuples": rate(x1.shape[0], c1_t[0]),
+            "scan_gtuples_1thread": rate(x1.shape[0], c1_1[0]),
+            "lookup_mrows": round(c1["ids"].shape[0] / c1_t[1] / 1e6, 3),
+            "lookup_mrows_1thread": round(c1["ids"].shape[0] / c1_1[1] / 1e6, 3)},
     }
 
 
@@ -488,7 +756,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--rows", type=int, default=500_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=4_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=3_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--layouts", default=",".join(LAYOUTS))
     ap.add_argument("--no-lookup", action="store_true")
@@ -498,7 +766,20 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (a plain copy kernel to scale memory counters)")
+    ap.add_argument("--summarize-trace", metavar="DIR", help="write a kernel-trace summary of DIR (CPU only)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write an HBM-traffic summary of two counter runs (CPU only)")
+    ap.add_argument("--out", help="summary file to write")
     args = ap.parse_args()
+    if args.summarize_trace or args.summarize_pmc:
+        from datagen import workloads
+
+        preds = workloads.config2_predicates(args.rows)
+        if args.summarize_trace:
+            summarize_trace(args.summarize_trace, args.steps, args.warmup, TRACE_CMD, args.out, preds)
+        else:
+            summarize_counters(args.summarize_pmc[0], args.summarize_pmc[1], PMC_CMDS, args.out, preds)
+        return
     if args.workload != "scan":
         if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
             print("bench.py measures one GPU; run with --gpus 1", file=sys.stderr)
@@ -610,6 +891,7 @@ def main():
             "alg_bytes_per_launch": float(alg_b.mean()),
             "full_bytes_per_launch": float(full_b.mean()),
             "lookup_ms": float(dur[e + len(preds)]),
+            "lookup_alg_bytes_per_id": lookup_alg_bytes_per_id(cols[lay][0].info),
             "lookup_mrows": (ids.shape[0] / (dur[e + len(preds)] * 1e-3) / 1e6) if not args.no_lookup else None,
         }
         e += len(preds) + 1
@@ -628,6 +910,21 @@ def main():
         "alg_bytes_per_launch": r["alg_bytes_per_launch"],
         "avg_launch_ms": float(np.mean(r["scan_ms"])),
     }
+    lookup_roofline = None
+    if not args.no_lookup:
+        lk_gbs = r["lookup_alg_bytes_per_id"] * ids.shape[0] / (r["lookup_ms"] * 1e-3) / 1e9
+        lookup_roofline = {
+            "bound": "hbm",
+            "achieved": round(lk_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(lk_gbs / HBM_PEAK_GBS, 4),
+            "traffic": read_traffic("lookup_hbm_bytes_per_launch"),
+            "kernel": "k_lookup (PP-VBS)",
+            "alg_bytes_per_id": round(r["lookup_alg_bytes_per_id"], 1),
+            "ids_per_launch": int(ids.shape[0]),
+            "avg_launch_ms": r["lookup_ms"],
+        }
     out = {
         "metric": METRIC,
         "value": round(r["scan_gtuples"], 3),
@@ -650,12 +947,15 @@ def main():
             "layout_bytes": {lay: int(cols[lay][0].info.layout_bytes) for lay in layouts},
         },
         "roofline": roofline,
+        "lookup_roofline": lookup_roofline,
         "layouts": {lay: {
             "scan_gtuples": round(v["scan_gtuples"], 3),
             "scan_hbm_frac": round(v["alg_gbs"] / HBM_PEAK_GBS, 4),
             "alg_bytes_per_launch": round(v["alg_bytes_per_launch"]),
             "full_bytes_per_launch": round(v["full_bytes_per_launch"]),
             "lookup_mrows": None if v["lookup_mrows"] is None else round(v["lookup_mrows"], 1),
+            "lookup_hbm_frac": None if v["lookup_mrows"] is None else round(
+                v["lookup_alg_bytes_per_id"] * ids.shape[0] / (v["lookup_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         } for lay, v in res.items()},
         "lookup_mrows": None if r["lookup_mrows"] is None else round(r["lookup_mrows"], 1),
         "p99_ms": None,
@@ -692,7 +992,7 @@ def main():
         progress("serving: %s" % json.dumps(out["serving"]))
     if not args.no_cpu_baseline:
         progress("cpu baseline (oracle) on %d rows" % args.cpu_sample)
-        out["cpu_baseline"] = cpu_baseline(x, preds, min(args.cpu_sample, n))
+        out["cpu_baseline"] = cpu_baseline(x, preds, ids, min(args.cpu_sample, n), _host_threads())
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

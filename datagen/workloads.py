@@ -89,6 +89,11 @@ def config2(n: int = 500_000_000, threads=None, n_ids: int | None = None):
     return {"x": x, "w": 20, "preds": preds, "ids": ids}
 
 
+def config2_predicates(n: int = 500_000_000, threads=None):
+    """The predicates of config2 alone (the column is regenerated to pick them)."""
+    return predicate_set(zipf_column(n, 20, 1.0, seed=2, threads=threads), 20)
+
+
 # config3: a wide table -- 16 columns of n rows; column c has width
 # [8, 12, 16, 20, 24, 32][c % 6] and Zipf exponent [0, 0.5, 1.0, 1.5][c % 4]
 # (0 = uniform), seed c.  The query pipelines '<' on columns 2, 5, 7, 9, each at
