@@ -411,36 +411,48 @@ def serve_queries(x_counts, layouts, n_queries: int, seed: int):
     return qs
 
 
-def serve_bench(dev_cols, x_counts, n_queries: int, budget_bytes: int):
-    """Saturation throughput of the continuous-batching server, then p50/p99 under
-    Poisson arrivals at half of it, served and one query at a time."""
+def serve_bench(dev_cols, x_counts, n_queries: int, budget_bytes: int, **server_kw):
+    """Saturation throughput (all queries at once) of the continuous-batching
+    server and of one query at a time, then p50/p99 of both under Poisson
+    arrivals at 25, 50 and 80 % of the one-at-a-time saturation."""
     from paper_2209_00220_amd.serve import GpuExecutor, Server, latency_summary, poisson_arrivals, run_serial
 
     layouts = list(dev_cols)
     ex = GpuExecutor({"t": dev_cols})
     warm = serve_queries(x_counts, layouts, 8, seed=99)
-    Server(ex, budget_bytes).run(warm, keep_values=False)
+    Server(ex, budget_bytes, **server_kw).run(warm, keep_values=False)
+    run_serial(ex, warm, keep_values=False)
     qs = serve_queries(x_counts, layouts, n_queries, seed=5)
-    sat = latency_summary(Server(ex, budget_bytes).run(qs, keep_values=False))
+    sat = latency_summary(Server(ex, budget_bytes, **server_kw).run(qs, keep_values=False))
     sat_serial = latency_summary(run_serial(ex, qs, keep_values=False))
-    qps = 0.5 * sat["qps"]
-    arr = poisson_arrivals(n_queries, qps, seed=6)
-    for q, a in zip(qs, arr):
-        q.arrival = float(a)
-    srv = Server(ex, budget_bytes)
-    served = latency_summary(srv.run(qs, keep_values=False))
-    serial = latency_summary(run_serial(ex, qs, keep_values=False))
+    loads = []
+    for frac in (0.25, 0.5, 0.8):
+        qps = frac * sat_serial["qps"]
+        for q, a in zip(qs, poisson_arrivals(n_queries, qps, seed=6)):
+            q.arrival = float(a)
+        srv = Server(ex, budget_bytes, **server_kw)
+        served = latency_summary(srv.run(qs, keep_values=False))
+        serial = latency_summary(run_serial(ex, qs, keep_values=False))
+        loads.append({"load": frac, "offered_qps": round(qps, 1),
+                      "p50_ms": round(served["p50_ms"], 3), "p99_ms": round(served["p99_ms"], 3),
+                      "one_at_a_time_p50_ms": round(serial["p50_ms"], 3),
+                      "one_at_a_time_p99_ms": round(serial["p99_ms"], 3),
+                      "mean_batch": round(sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)), 2)})
+    mid = loads[1]
+    for q in qs:
+        q.arrival = 0.0
     return {
         "queries": n_queries,
         "budget_bytes": budget_bytes,
         "saturation_qps": round(sat["qps"], 1),
         "saturation_qps_one_at_a_time": round(sat_serial["qps"], 1),
-        "offered_qps": round(qps, 1),
-        "p50_ms": round(served["p50_ms"], 3),
-        "p99_ms": round(served["p99_ms"], 3),
-        "one_at_a_time_p50_ms": round(serial["p50_ms"], 3),
-        "one_at_a_time_p99_ms": round(serial["p99_ms"], 3),
-        "mean_batch": round(sum(srv.batch_sizes) / max(1, len(srv.batch_sizes)), 2),
+        "offered_qps": mid["offered_qps"],
+        "p50_ms": mid["p50_ms"],
+        "p99_ms": mid["p99_ms"],
+        "one_at_a_time_p50_ms": mid["one_at_a_time_p50_ms"],
+        "one_at_a_time_p99_ms": mid["one_at_a_time_p99_ms"],
+        "mean_batch": mid["mean_batch"],
+        "loads": loads,
     }
 
 
@@ -570,10 +582,15 @@ def batch_main(args):
         for (c, op, lo, hi, _), o in zip(preds, outs):
             cols[c].scan(op, lo, hi, out=o)
 
+    # the single launches at their own best launch shape (also used by the batch's items)
+    from paper_2209_00220_amd.batch import autotune_scan
+
+    tuned, _ = autotune_scan([(cols[c], op, lo, hi) for c, op, lo, hi, _ in preds])
+    progress("scan launch tuned: grid %d, gather %d" % tuned)
     single_ms = _ms_events(singles)
     b = Batch([(cols[c], op, lo, hi, None) for c, op, lo, hi, _ in preds], outs)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    best, table = autotune(b, grids=[cus * 4, cus * 8, cus * 16], grabs=(8, 16, 32, 64), repeats=3)
+    best, table = autotune(b, grids=[cus * 2, cus * 3, cus * 4, cus * 8], grabs=(8, 16, 32, 64), repeats=3)
     batch_ms = time_call(lambda: b.launch(best[0], best[1], True), repeats=5)
     torch.cuda.synchronize()
     # every result's popcount against the plain count from the value counts
@@ -604,8 +621,8 @@ def batch_main(args):
 
 
 def serve_main(args):
-    """Serving workload: tables of 4 resident PP-VBS columns (rows log-uniform in
-    [--serve-rows-lo, --serve-rows-hi], w in 8..32, Zipf s in [0.5, 1.5]);
+    """Serving workload: tables of 4 resident PP-VBS columns (rows uniform in
+    [--serve-rows-lo, --serve-rows-hi], 4e8..1e9 by default; w in 8..32, Zipf s in [0.5, 1.5]);
     queries of 1-4 predicates and a lookup of 1-2 columns.  Saturation
     throughput and p50/p99 under Poisson arrivals at 25/50/80 % of the
     one-query-at-a-time saturation, served with continuous batching and one
@@ -619,20 +636,25 @@ def serve_main(args):
     from paper_2209_00220_amd.serve import GpuExecutor, Query, Server, latency_summary, poisson_arrivals, run_serial
 
     torch.cuda.set_device(0)
-    spec = workloads.config5_tables(args.serve_tables, 4, args.serve_rows_lo, args.serve_rows_hi)
+    spec = workloads.config5_tables(args.serve_tables, 4, args.serve_rows_lo, args.serve_rows_hi,
+                                    log_uniform=args.serve_log_uniform)
     tables, counts, keep = {}, [], []
     rows_total = 0
     for t, (n, cols) in enumerate(spec):
         tables["t%d" % t], cs = {}, []
         for c, (w, sk, seed) in enumerate(cols):
+            # one column at a time: raw values are freed once encoded; the value
+            # counts (for literal picking) come from the column's dictionary
             x = datagen.zipf_column(n, w, sk, seed=seed)
-            cs.append(workloads.value_counts(x, w))
             d = Dictionary(x)
+            del x
+            cs.append(d.values_counts())
             hc = HostColumn.encode(d, "ppvbs")
             d.close()
             tables["t%d" % t]["c%d" % c] = DeviceColumn(hc)
             keep.append(hc)
-            del x
+            progress("table %d column %d: %d rows, w=%d, s=%.2f, %.2f bytes/row" % (
+                t, c, n, w, sk, hc.info.layout_bytes / max(1, n)))
         counts.append(cs)
         rows_total += 4 * n
         progress("table %d / %d: %d rows x 4 columns" % (t + 1, len(spec), n))
@@ -657,19 +679,23 @@ def serve_main(args):
         qps = frac * sat_serial["qps"]
         for q, a in zip(qs, poisson_arrivals(len(qs), qps, seed=57)):
             q.arrival = float(a)
-        a = latency_summary(Server(ex, budget).run(qs, keep_values=False))
+        s_l = Server(ex, budget)
+        a = latency_summary(s_l.run(qs, keep_values=False))
         b = latency_summary(run_serial(ex, qs, keep_values=False))
-        loads.append({"offered_qps": round(qps, 1), "p50_ms": round(a["p50_ms"], 3), "p99_ms": round(a["p99_ms"], 3),
-                      "one_at_a_time_p50_ms": round(b["p50_ms"], 3), "one_at_a_time_p99_ms": round(b["p99_ms"], 3)})
+        loads.append({"load": frac, "offered_qps": round(qps, 1), "p50_ms": round(a["p50_ms"], 3),
+                      "p99_ms": round(a["p99_ms"], 3), "one_at_a_time_p50_ms": round(b["p50_ms"], 3),
+                      "one_at_a_time_p99_ms": round(b["p99_ms"], 3),
+                      "mean_batch": round(sum(s_l.batch_sizes) / max(1, len(s_l.batch_sizes)), 2)})
         progress("load %.0f%%: %s" % (100 * frac, json.dumps(loads[-1])))
     out = {
         "metric": "served queries/s at saturation (continuous batching vs one query at a time); p50/p99 under load",
         "value": round(sat["qps"], 1), "unit": "queries/s", "n_gpus": 1, "higher_is_better": True,
         "dtype": "u8", "data": "synthetic",
-        "config": {"workload": "%d tables x 4 PP-VBS columns, rows log-uniform in [%.0e, %.0e] per table, "
+        "config": {"workload": "%d tables x 4 PP-VBS columns, rows %s in [%.0e, %.0e] per table, "
                                "w in 8..32, Zipf s in [0.5, 1.5]; %d queries of 1-4 predicates "
                                "(<, >=, BETWEEN; selectivity log-uniform 0.01-50%%) + lookup of 1-2 columns"
-                               % (len(spec), args.serve_rows_lo, args.serve_rows_hi, len(qs)),
+                               % (len(spec), "log-uniform" if args.serve_log_uniform else "uniform",
+                                  args.serve_rows_lo, args.serve_rows_hi, len(qs)),
                    "rows_resident": rows_total, "resident_bytes": resident, "budget_bytes": budget},
         "saturation_qps_one_at_a_time": round(sat_serial["qps"], 1),
         "speedup": round(sat["qps"] / sat_serial["qps"], 3),
@@ -747,8 +773,9 @@ def main():
                          "serve: continuous batching over resident tables; "
                          "sweep: skew x domain (and Gaussian variance) sensitivity of every layout")
     ap.add_argument("--serve-tables", type=int, default=8)
-    ap.add_argument("--serve-rows-lo", type=float, default=1e6)
-    ap.add_argument("--serve-rows-hi", type=float, default=1e8)
+    ap.add_argument("--serve-rows-lo", type=float, default=4e8)
+    ap.add_argument("--serve-rows-hi", type=float, default=1e9)
+    ap.add_argument("--serve-log-uniform", action="store_true", help="table rows log-uniform (default uniform)")
     ap.add_argument("--sweep-rows", type=int, default=50_000_000)
     ap.add_argument("--wide-rows", type=int, default=100_000_000)
     ap.add_argument("--batch-cols", type=int, default=64)
@@ -760,10 +787,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--layouts", default=",".join(LAYOUTS))
     ap.add_argument("--no-lookup", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in scan launch shape")
     ap.add_argument("--preds", default="", help="comma-separated predicate indices to run (profiling)")
     ap.add_argument("--serve-queries", type=int, default=200, help="queries of the serving run (0: skip)")
     ap.add_argument("--no-batch", dest="batch", action="store_false", help="skip the batched-launch measurement")
-    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device (a plain copy kernel to scale memory counters)")
     ap.add_argument("--summarize-trace", metavar="DIR", help="write a kernel-trace summary of DIR (CPU only)")
@@ -838,6 +866,17 @@ def main():
             c = ctr.cpu().numpy()
             alg[(lay, i)] = (int(c[0]), int(c[3]))
     progress("counters done")
+    tune_info = None
+    if not args.no_tune:
+        # launch shape of the single-column scans (grid, later-level gather limit),
+        # timed on this step's own scans before the timed region
+        from paper_2209_00220_amd.batch import autotune_scan
+
+        tuned, table = autotune_scan([(cols[lay][1], op, lo, hi) for lay in layouts for op, lo, hi, _ in preds])
+        tune_info = {"scan_grid": int(tuned[0]), "gather_rows": int(tuned[1]),
+                     "candidates_ms": {"%d/%d" % k: round(v, 3) for k, v in sorted(table.items())}}
+        progress("scan launch tuned: grid %d, gather %d (%s)" % (
+            tuned[0], tuned[1], ", ".join("%d/%d: %.2f ms" % (g, r, t) for (g, r), t in sorted(table.items()))))
 
     stream = torch.cuda.current_stream()
     n_ev = len(layouts) * (len(preds) + 1)
@@ -947,6 +986,7 @@ def main():
             "layout_bytes": {lay: int(cols[lay][0].info.layout_bytes) for lay in layouts},
         },
         "roofline": roofline,
+        "scan_tuning": tune_info,
         "lookup_roofline": lookup_roofline,
         "layouts": {lay: {
             "scan_gtuples": round(v["scan_gtuples"], 3),
@@ -975,7 +1015,7 @@ def main():
         outs = [cols[layouts[0]][1].new_bv() for _ in specs]
         b = Batch(specs, outs)
         cus = torch.cuda.get_device_properties(0).multi_processor_count
-        best, table = autotune(b, grids=[cus * 4, cus * 8, cus * 16], grabs=(8, 16, 32, 64), repeats=3)
+        best, table = autotune(b, grids=[cus * 2, cus * 3, cus * 4, cus * 8], grabs=(8, 16, 32, 64), repeats=3)
         batch_ms = time_call(lambda: b.launch(best[0], best[1], True), repeats=5)
         single_ms = float(sum(sum(res[lay]["scan_ms"]) for lay in layouts))
         out["batch"] = {"scans": len(specs), "grid": best[0], "tiles_per_grab": best[1],

@@ -139,6 +139,8 @@ typedef struct {
     int mapping;   /* 0 scatter, 1 sorted */
     int method;    /* 0 uniform, 1 table, 2 rejection-inversion */
     const double* cdf;
+    const uint32_t* guide;   /* guide[b] = first index with cdf > b / ng */
+    uint64_t ng;
     zri_t zri;
     perm_t perm;
 } job_t;
@@ -151,7 +153,13 @@ static void* fill_worker(void* arg) {
             k = 1 + (uint64_t)(((__uint128_t)draw(j->seed, i << 12) * j->nvals) >> 64);
         } else if (j->method == 1) {
             double u = draw_unit(j->seed, i << 12);
-            uint64_t lo = 0, hi = j->nvals - 1; /* first idx with cdf[idx] > u */
+            /* first idx with cdf[idx] > u, searched between the guide entries of
+               the bucket of u (the same index a search of the whole table finds) */
+            uint64_t b = (uint64_t)(u * (double)j->ng);
+            if (b >= j->ng) b = j->ng - 1;
+            while (b > 0 && (double)b / (double)j->ng > u) --b;
+            while (b + 1 < j->ng && (double)(b + 1) / (double)j->ng <= u) ++b;
+            uint64_t lo = j->guide[b], hi = j->guide[b + 1];
             while (lo < hi) {
                 uint64_t mid = (lo + hi) >> 1;
                 if (j->cdf[mid] > u) hi = mid; else lo = mid + 1;
@@ -185,6 +193,7 @@ int dg_zipf_u32(uint32_t* out, uint64_t n, uint32_t w, double s, uint64_t seed,
     base.mapping = mapping;
     base.perm = perm_make(w, seed);
     double* cdf = NULL;
+    uint32_t* guide = NULL;
     if (s == 0.0) {
         base.method = 0;
     } else if (w <= 24) {
@@ -201,6 +210,21 @@ int dg_zipf_u32(uint32_t* out, uint64_t n, uint32_t w, double s, uint64_t seed,
         }
         cdf[nv - 1] = 2.0; /* guard: every u < 1 lands inside */
         base.cdf = cdf;
+        /* guide table: bucket b of [0, 1) starts its search at the first index
+           whose cdf exceeds b / ng; the last entry closes the final bucket */
+        base.ng = nv < (1ULL << 22) ? nv : (1ULL << 22);
+        guide = (uint32_t*)malloc(sizeof(uint32_t) * (base.ng + 1));
+        if (!guide) {
+            free(cdf);
+            return -1;
+        }
+        uint64_t idx = 0;
+        for (uint64_t b = 0; b < base.ng; ++b) {
+            while (cdf[idx] <= (double)b / (double)base.ng) ++idx;
+            guide[b] = (uint32_t)idx;
+        }
+        guide[base.ng] = (uint32_t)(nv - 1);
+        base.guide = guide;
     } else {
         base.method = 2;
         base.zri = zri_make(s, (double)nv);
@@ -225,6 +249,7 @@ int dg_zipf_u32(uint32_t* out, uint64_t n, uint32_t w, double s, uint64_t seed,
     for (uint32_t t = 0; t < nthreads; ++t)
         if (threaded[t]) pthread_join(th[t], NULL);
     free(cdf);
+    free(guide);
     return 0;
 }
 

@@ -145,14 +145,16 @@ def config4_predicates(counts, n_preds: int = 256, seed: int = 5):
     return out
 
 
-def config5_tables(n_tables: int = 8, n_cols: int = 4, n_lo: float = 1e6, n_hi: float = 1e8, seed: int = 55):
-    """Tables for the serving workload: n_t log-uniform in [n_lo, n_hi] (every
-    column of a table has n_t rows), width w ~ U{8..32}, Zipf s ~ U[0.5, 1.5].
-    Returns [(n_t, [(w, s, seed), ...])]."""
+def config5_tables(n_tables: int = 8, n_cols: int = 4, n_lo: float = 4e8, n_hi: float = 1e9, seed: int = 55,
+                   log_uniform: bool = False):
+    """Tables for the serving workload: n_t uniform in [n_lo, n_hi] (log-uniform
+    when asked; every column of a table has n_t rows), width w ~ U{8..32},
+    Zipf s ~ U[0.5, 1.5].  Returns [(n_t, [(w, s, seed), ...])]."""
     rng = np.random.default_rng(seed)
     out = []
     for t in range(n_tables):
-        n = int(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        u = rng.uniform(0.0, 1.0)
+        n = int(np.exp(np.log(n_lo) + u * (np.log(n_hi) - np.log(n_lo)))) if log_uniform else int(n_lo + u * (n_hi - n_lo))
         cols = [(int(rng.integers(8, 33)), float(rng.uniform(0.5, 1.5)), 500 + 10 * t + c) for c in range(n_cols)]
         out.append((n, cols))
     return out

@@ -232,6 +232,17 @@ int bst_scan_stats(const bst_column* col, bst_pred pred, const uint64_t* in_mask
  */
 int bst_lookup(const bst_column* col, const uint32_t* row_ids, uint64_t m, uint32_t* out_values,
                uint32_t* dev_status, void* stream);
+/*
+ * Lookup by a device-resident row-ID list whose length is itself on the device
+ * (as bst_bv_compact leaves it): out_values[i] = value of row row_ids[i] for
+ * i < *dev_count, when *dev_count <= cap.  So the IDs of one compaction serve
+ * lookups of several columns of the same rows with no host read of the count.
+ * All or nothing: when *dev_count > cap nothing is written and BST_DEV_OVERFLOW
+ * is set in *dev_status (may be NULL); the caller looks up again with a cap
+ * of at least the count.  A row ID >= n_rows yields 0 and sets BST_DEV_BAD_ROW.
+ */
+int bst_lookup_counted(const bst_column* col, const uint32_t* row_ids, const uint64_t* dev_count, uint64_t cap,
+                       uint32_t* out_values, uint32_t* dev_status, void* stream);
 /* Workspace bytes bst_bv_compact / bst_lookup_bv need for n_rows rows. */
 uint64_t bst_compact_workspace_bytes(uint64_t n_rows);
 /*

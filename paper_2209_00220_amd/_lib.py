@@ -80,6 +80,7 @@ _PROTOS = {
     "bst_bv_compact": (_I, [_P, _U64, _P, _U64, _P, _P, _P, _P]),
     "bst_lookup_bv": (_I, [_P, _P, _P, _U64, _P, _P, _P, _P, _P]),
     "bst_lookup_bv_static": (_I, [_P, _P, _P, _U64, _P, _P, _P]),
+    "bst_lookup_counted": (_I, [_P, _P, _P, _U64, _P, _P, _P]),
     "bst_lookup_bv_static_max_rows": (_U64, []),
     "bst_lookup_bv_static_max_ids": (_U64, []),
     "bst_bv_and": (_I, [_P, _P, _P, _U64, _P]),
@@ -265,6 +266,10 @@ def bst_bv_compact(bv, n_rows, out_ids, cap, dev_count, workspace, dev_status, s
 def bst_lookup_bv(col, bv, out_values, cap, dev_count, ids_tmp, workspace, dev_status, stream):
     _call("bst_lookup_bv", col, _ptr(bv), _ptr(out_values), cap, _ptr(dev_count), _ptr(ids_tmp),
           _ptr(workspace), _ptr(dev_status), stream)
+
+
+def bst_lookup_counted(col, row_ids, dev_count, cap, out_values, dev_status, stream):
+    _call("bst_lookup_counted", col, _ptr(row_ids), _ptr(dev_count), cap, _ptr(out_values), _ptr(dev_status), stream)
 
 
 def bst_lookup_bv_static(col, bv, out_values, cap, dev_count, dev_status, stream):

@@ -41,7 +41,7 @@ def advise_column(x, numeric: bool = True, width: int = 0, layouts=("byteslice",
     lits, sels = d.profile_literals(op, count)
     cols = {}
     for lay in layouts:
-        hc = HostColumn.encode(d, lay, width=width if lay != "ppvbs" else 0)
+        hc = HostColumn.encode(d, lay, width=width if not lay.startswith("ppvbs") else 0)
         cols[lay] = (hc, DeviceColumn(hc))
     scratch = torch.empty(nwords(d.n_rows), dtype=torch.int64, device="cuda")
     chosen_idx, aucs, times = L.bst_advise([cols[l][1].h for l in layouts], op, lits, sels, repeats, scratch,

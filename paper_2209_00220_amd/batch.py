@@ -84,16 +84,33 @@ def autotune(batch: Batch, grids=None, grabs=(1, 2, 4, 8, 16), repeats: int = 5,
     return best, results
 
 
-def autotune_scan_grid(col, op="lt", lo=0, hi=None, grids=None, repeats: int = 5):
-    """Pick the single-column scan grid (workgroups per launch) by timing."""
+def autotune_scan(scans, grids=None, gathers=(1, 2, 4), repeats: int = 3):
+    """Pick the single-column scan launch shape by timing: every (grid, gather)
+    pair runs all `scans` -- (DeviceColumn, op, lo, hi) -- and the pair with the
+    smallest total time is stored as the library's default.  grid: workgroups
+    per scan launch (0 keeps each layout's built-in default); gather: pending
+    rows per 32-row lane that a later level gathers one by one before the tile
+    stages the level's run in LDS instead.  Returns (best pair, {pair: ms})."""
     if grids is None:
         cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
-        grids = [cus * k for k in (2, 4, 8, 16, 32)]
-    out = col.new_bv()
+        grids = [0] + [cus * k for k in (2, 3, 4, 6)]
+    outs = [s[0].new_bv() for s in scans]
+
+    def run():
+        for (col, op, lo, hi), o in zip(scans, outs):
+            col.scan(op, lo, hi, out=o)
+
+    saved = (L.bst_tune_get(L.TUNE_SCAN_GRID), L.bst_tune_get(L.TUNE_GATHER_ROWS))
     results = {}
-    for g in grids:
-        L.bst_tune_set(L.TUNE_SCAN_GRID, g)
-        results[g] = time_call(lambda: col.scan(op, lo, hi, out=out), repeats=repeats)
+    try:
+        for g, r in itertools.product(grids, gathers):
+            L.bst_tune_set(L.TUNE_SCAN_GRID, g)
+            L.bst_tune_set(L.TUNE_GATHER_ROWS, r)
+            results[(g, r)] = time_call(run, repeats=repeats)
+    finally:
+        L.bst_tune_set(L.TUNE_SCAN_GRID, saved[0])
+        L.bst_tune_set(L.TUNE_GATHER_ROWS, saved[1])
     best = min(results, key=results.get)
-    L.bst_tune_set(L.TUNE_SCAN_GRID, best)
+    L.bst_tune_set(L.TUNE_SCAN_GRID, best[0])
+    L.bst_tune_set(L.TUNE_GATHER_ROWS, best[1])
     return best, results

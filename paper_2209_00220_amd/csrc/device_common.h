@@ -238,19 +238,20 @@ __device__ __forceinline__ void scan_packed_range(const DevCol& c, const PackedL
 // Value of one row (Sec. 3.3, lookup): gather the row's bytes, rebuild its
 // code, decode it.  PP-VBS finds the position of byte j in BS_j from M_j and the
 // directory instead of Algorithm 4's running cursors, so any row can be read on
-// its own; the decode tables walk Algorithm 1's tree: a slot ends the code, a
-// pointer descends, a leaf turns the remaining bytes into a slot number.
-__device__ __forceinline__ uint32_t trie_rank(const DevCol& c, uint64_t code, uint32_t len) {
+// its own; the decode tables walk Algorithm 1's tree: a slot ends the code (and
+// holds its value), a pointer descends, a leaf turns the remaining bytes into a
+// slot number (a rank into the dictionary).
+__device__ __forceinline__ uint32_t trie_value(const DevCol& c, uint64_t code, uint32_t len) {
     uint32_t ch = c.trie_root;
     for (uint32_t j = 1;; ++j) {
-        if (ch & kLeafFlag) {
+        if (ch & kLeafFlag) {   // a leaf: the remaining bytes number a slot of consecutive ranks
             const uint32_t rest = len - j + 1;
             const uint64_t slot = rest >= 8 ? code : (code & ((1ull << (8 * rest)) - 1));
-            return (ch & ~kLeafFlag) + (uint32_t)slot - 1u;
+            return c.dict[(ch & ~kLeafFlag) + (uint32_t)slot - 1u];
         }
         const uint32_t byte = (uint32_t)(code >> (8 * (len - j))) & 0xffu;
         const uint32_t* e = c.trie + ((uint64_t)ch * 256 + byte) * 2;
-        if (j >= len) return e[0];
+        if (j >= len) return e[0];   // the code ends in this slot: its value
         ch = e[1];
     }
 }
@@ -281,7 +282,7 @@ __device__ __forceinline__ uint32_t lookup_row(const DevCol& c, uint64_t r) {
             len = j;
         }
         if (c.categorical) return c.dict[categorical_rank(code, len, c.K)];
-        return c.dict[trie_rank(c, code, len)];
+        return trie_value(c, code, len);
     }
     if (c.layout == BST_BYTESLICE) {
         uint64_t v = c.bs[1][pos1];
@@ -372,6 +373,7 @@ int launch_packed(const DevCol& c, const PackedLit& pl, const uint64_t* in, uint
 int run_scan(const bst_column* col, const ScanLit& lit, const uint64_t* in, uint64_t* out,
              unsigned long long* counters, hipStream_t st);
 uint32_t batch_kind(const bst_column* col, const ScanLit& lit);
+uint32_t lookup_grid(uint64_t m);
 int enqueue_fill(uint64_t* out, const uint64_t* in, uint64_t n, int all, hipStream_t st);
 
 }  // namespace dev

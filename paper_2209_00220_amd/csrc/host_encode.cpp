@@ -175,7 +175,8 @@ struct PpeBuilder {
     const std::vector<uint64_t>& Q;
     std::vector<uint64_t>& C;
     std::vector<uint8_t>& L;
-    std::vector<uint32_t>& trie;   // 512 uint32 per node: (slot rank, child) x 256
+    std::vector<uint32_t>& trie;   // 512 uint32 per node: (slot rank, child) x 256; the
+                                   // encoder replaces each slot rank by the slot's value
     std::vector<uint32_t> idx;     // scratch for the top-255 selection
 
     static uint32_t digits(uint64_t count) {   // smallest beta with 256^beta >= count
@@ -442,6 +443,10 @@ static int encode_column(const Dict& d, int layout, uint32_t width, uint32_t dir
         c.width = 8 * K;
         c.buf[BST_BUF_DICT].resize(c.nd * 4);
         if (c.nd) memcpy(c.buf[BST_BUF_DICT].data(), c.dict.data(), c.nd * 4);
+        // slot entries carry the slot's value rather than its rank, so a lookup of
+        // a code that ends in a slot needs no dictionary read
+        for (size_t k = 0; k < trie.size(); k += 2)
+            if (k % 512 != 0) trie[k] = c.dict[trie[k]];
         c.buf[BST_BUF_TRIE].resize(trie.size() * 4);
         if (!trie.empty()) memcpy(c.buf[BST_BUF_TRIE].data(), trie.data(), trie.size() * 4);
         build_vbs(c, d.rank.data(), T);

@@ -177,11 +177,20 @@ __global__ __launch_bounds__(kBlock) void k_write_ids(const uint64_t* __restrict
 }
 
 
+// all_or_none: with a device count above cap, look up nothing and flag the overflow
 __global__ __launch_bounds__(kBlock) void k_lookup(const DevCol c, const uint32_t* __restrict__ ids, uint64_t m,
                                                    const unsigned long long* __restrict__ dev_m, uint64_t cap,
-                                                   uint32_t* __restrict__ out, uint32_t* __restrict__ status) {
+                                                   uint32_t* __restrict__ out, uint32_t* __restrict__ status,
+                                                   int all_or_none) {
     uint64_t cnt = m;
-    if (dev_m) cnt = std::min<uint64_t>((uint64_t)*dev_m, cap);
+    if (dev_m) {
+        const uint64_t dm = (uint64_t)*dev_m;
+        if (all_or_none && dm > cap) {
+            if (status && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(status, BST_DEV_OVERFLOW);
+            return;
+        }
+        cnt = std::min<uint64_t>(dm, cap);
+    }
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t r = ids[i];
         if (r >= c.n) {
@@ -238,6 +247,14 @@ PackedLit packed_literal(const HostColumn& h, const ScanLit& s) {
             break;
     }
     return p;
+}
+
+// Workgroups of a lookup launch: 4 per CU by default (measured a few percent
+// faster than 16 per CU on random row IDs), or the tuned count.
+uint32_t lookup_grid(uint64_t m) {
+    if (g_tune[BST_TUNE_LOOKUP_GRID] > 0) return (uint32_t)g_tune[BST_TUNE_LOOKUP_GRID];
+    const uint64_t want = (m + kBlock - 1) / kBlock;
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)props().cus * 4));
 }
 
 int enqueue_fill(uint64_t* out, const uint64_t* in, uint64_t n, int all, hipStream_t st) {
@@ -363,9 +380,20 @@ int bst_lookup(const bst_column* col, const uint32_t* row_ids, uint64_t m, uint3
     if (m == 0) return BST_OK;
     if (!row_ids || !out_values) return set_error(BST_EINVAL, "NULL argument");
     if (col->host->codes_only) return set_error(BST_EUNSUPPORTED, "lookup on a column built from explicit codes");
-    const uint32_t grid = g_tune[BST_TUNE_LOOKUP_GRID] > 0 ? (uint32_t)g_tune[BST_TUNE_LOOKUP_GRID] : elem_grid(m);
+    const uint32_t grid = lookup_grid(m);
     hipLaunchKernelGGL(k_lookup, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, col->dev, row_ids, m,
-                       (const unsigned long long*)nullptr, m, out_values, dev_status);
+                       (const unsigned long long*)nullptr, m, out_values, dev_status, 0);
+    return hip_check(hipGetLastError(), "lookup launch");
+}
+
+int bst_lookup_counted(const bst_column* col, const uint32_t* row_ids, const uint64_t* dev_count, uint64_t cap,
+                       uint32_t* out_values, uint32_t* dev_status, void* stream) {
+    if (!col) return set_error(BST_EINVAL, "NULL column");
+    if (cap == 0) return BST_OK;
+    if (!row_ids || !dev_count || !out_values) return set_error(BST_EINVAL, "NULL argument");
+    if (col->host->codes_only) return set_error(BST_EUNSUPPORTED, "lookup on a column built from explicit codes");
+    hipLaunchKernelGGL(k_lookup, dim3(lookup_grid(cap)), dim3(kBlock), 0, (hipStream_t)stream, col->dev, row_ids, cap,
+                       (const unsigned long long*)dev_count, cap, out_values, dev_status, 1);
     return hip_check(hipGetLastError(), "lookup launch");
 }
 
@@ -407,9 +435,9 @@ int bst_lookup_bv(const bst_column* col, const uint64_t* bv, uint32_t* out_value
     if (rc) return rc;
     if (cap == 0) return BST_OK;
     if (!out_values) return set_error(BST_EINVAL, "NULL output");
-    const uint32_t grid = g_tune[BST_TUNE_LOOKUP_GRID] > 0 ? (uint32_t)g_tune[BST_TUNE_LOOKUP_GRID] : elem_grid(cap);
+    const uint32_t grid = lookup_grid(cap);
     hipLaunchKernelGGL(k_lookup, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, col->dev, ids_tmp, cap,
-                       (const unsigned long long*)dev_count, cap, out_values, dev_status);
+                       (const unsigned long long*)dev_count, cap, out_values, dev_status, 0);
     return hip_check(hipGetLastError(), "lookup launch");
 }
 

@@ -8,31 +8,42 @@ result into the next as its incoming mask, Sec. 3.3).  Every column stays
 resident in device memory.  The server runs in steps:
 
 * admission: arrived queries enter in arrival order while the device bytes
-  they need fit the budget -- two result bitvectors of ceil(n/64) words, and
-  later 8 bytes per qualifying row per lookup column (values plus row IDs).
-  The bitvectors of scanning queries may hold only a share of the budget
-  (half by default), so the lookups of finished queries always find room and
-  a queue of new arrivals cannot starve them;
+  they reserve fit the budget: two result bitvectors of ceil(n/64) words, and
+  the lookup outputs for its qualifying rows (4-byte values per lookup column
+  and 4-byte row IDs; every row of the table by default, or up to
+  ``lookup_cap_rows``).  These reservations may hold
+  only a share of the budget (half by default), so a query whose rows exceed
+  its reservation always finds room to finish, and a queue of new arrivals
+  cannot starve it;
 * scan step: admitted queries that still have predicates contribute their
   next one, with the previous result as the incoming mask, to ONE batched
   launch (a persistent kernel over all their tiles).  The oldest queries go
-  first, and a step stops adding queries once it covers enough rows to fill
-  the device by itself (``step_rows``): so a query advances one predicate per
-  step, small scans share launches, and a large scan is not slowed by
-  sharing the device with later queries;
-* lookup: a query whose predicates are done counts its rows, gathers the
-  values of its lookup columns, and completes.
+  first, and a step stops adding queries once its scans cover ``step_rows``
+  rows (2^27 by default, about what fills the device): so a query advances one
+  predicate per step, the scans of small tables share launches, and a scan
+  that fills the device by itself is not stretched by sharing a launch with
+  later queries (measured on a 500M-row column: merging such scans cut the
+  saturation throughput by a quarter and multiplied the p50 at 80 % load);
+* finish: right behind a query's last scan, on the same stream, the executor
+  enqueues the compaction of its result (ascending row IDs and their count,
+  kept on the device), the lookups of its columns into the reserved outputs,
+  and an asynchronous copy of the count to the host.  No host round trip
+  separates a query's scans from its lookups, and the device runs every
+  query's work in arrival order, as one query at a time would, without the
+  gaps.  A query with more rows than its reservation reserves the exact bytes
+  once its count is known and looks up again.
 
 The loop never waits for the device while it has work to enqueue: each step
-and each set of lookups is followed by a fence (an event on the stream), the
-host reads counts and completes queries once their fences have passed, and
-keeps few scan steps in flight -- at most ``lookahead`` of them, covering at
-most ``lookahead_rows`` rows -- so that new arrivals join soon.  So the host's admission, counting and lookup set-up of some queries
-overlap the device's scans of others.
+and each finish is followed by an event, the host completes queries once
+their events have passed, and keeps few scan steps in flight -- at most
+``lookahead`` of them, covering at most ``lookahead_rows`` rows -- so that
+new arrivals join soon.
 
 Latency is completion time minus arrival time.  ``run_serial`` serves the
-same queries one at a time with single scans, waiting for each, the baseline
-continuous batching is measured against.
+same queries one at a time with the plain per-query calls (one scan launch
+per predicate, then the row count read back to size the lookup, then the
+lookups), waiting for each query: the baseline that continuous batching is
+measured against.
 
 The executor is an interface: ``GpuExecutor`` drives the HIP library; tests
 drive the same loop with a host executor.
@@ -71,42 +82,45 @@ class Result:
 
 
 class _Active:
-    __slots__ = ("q", "k", "cur", "nxt", "admitted", "reserved")
+    __slots__ = ("q", "k", "cur", "nxt", "admitted", "reserved", "cap")
 
-    def __init__(self, q, cur, nxt, admitted, reserved):
-        self.q, self.k, self.cur, self.nxt, self.admitted, self.reserved = q, 0, cur, nxt, admitted, reserved
+    def __init__(self, q, cur, nxt, admitted, reserved, cap):
+        self.q, self.k, self.cur, self.nxt, self.admitted, self.reserved, self.cap = q, 0, cur, nxt, admitted, reserved, cap
 
 
 class Server:
     """Continuous-batching server.
 
     executor: object with ``n_rows(table)``, ``bv_bytes(table)``, ``new_bv(table)``,
-    ``scan_step(items)``, ``count_rows(pairs)``, ``read_counts(handle)``,
-    ``lookup(table, column, bv, count)``, ``fence()``, ``is_done(token)`` and
-    ``wait(token)``.  ``scan_step`` takes a list of (table, column, op, lo, hi,
-    in_bv or None, out_bv), enqueues the scans and returns a token that marks
-    them; ``count_rows`` enqueues the row counts of (table, bv) pairs, ordered
-    after every scan enqueued so far, and returns a token that ``read_counts``
-    turns into ints once it is done; ``lookup`` enqueues a gather of the set
-    rows' values, ordered after the counts; ``fence`` marks the counts and
-    lookups enqueued so far; ``is_done`` tests a token without waiting and
-    ``wait`` waits for it.  Counts and lookups may run beside later scans.
+    ``scan_step(items)``, ``finish(table, bv, columns, cap)``, ``result(token)``,
+    ``is_done(token)`` and ``wait(token)``.  ``scan_step`` takes a list of
+    (table, column, op, lo, hi, in_bv or None, out_bv), enqueues the scans and
+    returns a token that marks them; ``finish`` enqueues, behind every scan so
+    far, the row count of bv and the values of `columns` for up to `cap` of its
+    rows, and returns a token; once that token is done, ``result`` gives
+    (count, {column: values}), or (count, None) when count > cap; ``is_done``
+    tests a token without waiting and ``wait`` waits for it.
     budget_bytes: device bytes the admitted queries may hold at once.  A query
     that alone exceeds the budget is still served once nothing else is admitted.
-    scan_share: fraction of the budget the bitvectors of admitted queries may
-    hold; the rest is kept for lookups.
-    max_batch: most scans per step.  step_rows: a step takes no further query
-    once its scans cover this many rows.  lookahead / lookahead_rows: most scan
-    steps, and most rows scanned by them, in flight (one step always may be).
+    scan_share: fraction of the budget the admission reservations (bitvectors
+    and lookup outputs) may hold; the rest is kept for queries whose rows
+    exceed their reservation.  lookup_cap_rows: qualifying rows whose lookup
+    outputs a query reserves at admission (None: all rows of its table, so no
+    lookup ever waits for a count; 0: none, every lookup waits for the count).
+    max_batch: most scans per step.  step_rows: a step takes no
+    further query once its scans cover this many rows.  lookahead /
+    lookahead_rows: most scan steps, and most rows scanned by them, in flight
+    (one step always may be).
     """
 
     def __init__(self, executor, budget_bytes: int, max_batch: int = 256, scan_share: float = 0.5,
                  step_rows: int = 1 << 27, lookahead: int = 8, lookahead_rows: int = 1 << 30,
+                 lookup_cap_rows: Optional[int] = None,
                  clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep):
         if (budget_bytes <= 0 or max_batch <= 0 or step_rows <= 0 or lookahead <= 0 or lookahead_rows <= 0
-                or not 0.0 < scan_share <= 1.0):
+                or (lookup_cap_rows is not None and lookup_cap_rows < 0) or not 0.0 < scan_share <= 1.0):
             raise ValueError("budget_bytes, max_batch, step_rows, lookahead and lookahead_rows must be "
-                             "positive, scan_share in (0, 1]")
+                             "positive, lookup_cap_rows non-negative, scan_share in (0, 1]")
         self.ex = executor
         self.budget = int(budget_bytes)
         self.scan_budget = max(1, int(budget_bytes * scan_share))
@@ -114,6 +128,7 @@ class Server:
         self.step_rows = int(step_rows)
         self.lookahead = int(lookahead)
         self.lookahead_rows = int(lookahead_rows)
+        self.lookup_cap_rows = None if lookup_cap_rows is None else int(lookup_cap_rows)
         self.clock = clock
         self.sleep = sleep
         self.in_use = 0
@@ -121,9 +136,13 @@ class Server:
         self.peak_in_use = 0
         self.steps = 0
         self.batch_sizes: List[int] = []
+        self.relookups = 0
 
-    def _scan_bytes(self, q: Query) -> int:
-        return 2 * self.ex.bv_bytes(q.table)
+    def _reservation(self, q: Query) -> Tuple[int, int]:
+        """(bytes, rows): two bitvectors, and lookup outputs for up to lookup_cap_rows rows."""
+        n = self.ex.n_rows(q.table)
+        cap = (n if self.lookup_cap_rows is None else min(n, self.lookup_cap_rows)) if q.lookups else 0
+        return 2 * self.ex.bv_bytes(q.table) + 4 * cap * (len(q.lookups) + 1), cap
 
     def run(self, queries: Sequence[Query], keep_values: bool = True) -> Dict[int, Result]:
         order = sorted(queries, key=lambda q: (q.arrival, q.qid))
@@ -135,11 +154,10 @@ class Server:
         nxt_arrival = 0
         waiting: collections.deque = collections.deque()
         scanning: List[_Active] = []          # admitted, predicates left, in admission order
-        steps: collections.deque = collections.deque()      # (seq, fence, rows) of scan steps in flight
+        steps: collections.deque = collections.deque()      # (seq, token, rows) of scan steps in flight
         inflight_rows = 0
-        counting: collections.deque = collections.deque()   # (seq, counts token, [_Active])
-        blocked: collections.deque = collections.deque()    # (_Active, count): lookup waits for memory
-        gathering: collections.deque = collections.deque()  # (seq, fence, [(a, count, extra, vals)])
+        finishing: collections.deque = collections.deque()  # (seq, token, _Active, extra bytes)
+        blocked: collections.deque = collections.deque()    # (_Active, count): rows beyond the reservation
         seq = 0
         done: Dict[int, Result] = {}
         while len(done) < len(order):
@@ -149,15 +167,15 @@ class Server:
                 nxt_arrival += 1
             # admission in arrival order (no overtaking: a large query blocks later ones)
             while waiting:
-                need = self._scan_bytes(waiting[0])
-                busy = scanning or counting or blocked or gathering
+                need, cap = self._reservation(waiting[0])
+                busy = scanning or finishing or blocked
                 if busy and (self.in_use + need > self.budget or self.scan_in_use + need > self.scan_budget):
                     break
                 q = waiting.popleft()
                 self.in_use += need
                 self.scan_in_use += need
                 self.peak_in_use = max(self.peak_in_use, self.in_use)
-                scanning.append(_Active(q, None, ex.new_bv(q.table), self.clock() - t0, need))
+                scanning.append(_Active(q, None, ex.new_bv(q.table), self.clock() - t0, need, cap))
             enqueued = False
             # one scan step: the next predicate of the oldest scanning queries, one launch
             while steps and ex.is_done(steps[0][1]):
@@ -191,41 +209,41 @@ class Server:
                 fin = [a for a in batch if a.k >= len(a.q.preds)]
                 if fin:
                     scanning = [a for a in scanning if a.k < len(a.q.preds)]
-                    seq += 1
-                    counting.append((seq, ex.count_rows([(a.q.table, a.cur) for a in fin]), fin))
+                    for a in fin:   # counts and lookups right behind the last scans, no host wait
+                        seq += 1
+                        finishing.append((seq, ex.finish(a.q.table, a.cur, a.q.lookups, a.cap), a, 0))
                 enqueued = True
-            # counts known: reserve lookup bytes and enqueue the gathers, oldest
-            # first; the oldest query always proceeds when no gather is in flight
-            while counting and ex.is_done(counting[0][1]):
-                _, handle, fin = counting.popleft()
-                blocked.extend(zip(fin, ex.read_counts(handle)))
-            started = []
-            while blocked:
-                a, count = blocked[0]
-                extra = 8 * int(count) * len(a.q.lookups)
-                if extra and self.in_use + extra > self.budget and (gathering or started):
-                    break
-                blocked.popleft()
-                self.in_use += extra
-                self.peak_in_use = max(self.peak_in_use, self.in_use)
-                vals = {c: ex.lookup(a.q.table, c, a.cur, int(count)) for c in a.q.lookups}
-                started.append((a, int(count), extra, vals))
-            if started:
-                seq += 1
-                gathering.append((seq, ex.fence(), started))
-                enqueued = True
-            # gathers finished: the queries complete
-            while gathering and ex.is_done(gathering[0][1]):
-                _, _, fin = gathering.popleft()
-                t = self.clock() - t0
-                for a, count, extra, vals in fin:
+            # finished work: complete the query, or look up again with the exact count
+            progress = True
+            while progress:
+                progress = False
+                while finishing and ex.is_done(finishing[0][1]):
+                    _, tok, a, extra = finishing.popleft()
+                    count, vals = ex.result(tok)
+                    progress = True
+                    if vals is None:
+                        blocked.append((a, count))
+                        continue
+                    t = self.clock() - t0
                     self.in_use -= extra + a.reserved
                     self.scan_in_use -= a.reserved
                     done[a.q.qid] = Result(a.q.qid, count, vals if keep_values else {}, a.q.arrival, a.admitted, t)
+                while blocked:
+                    a, count = blocked[0]
+                    extra = 4 * int(count) * (len(a.q.lookups) + 1)
+                    if self.in_use + extra > self.budget and finishing:
+                        break
+                    blocked.popleft()
+                    self.in_use += extra
+                    self.peak_in_use = max(self.peak_in_use, self.in_use)
+                    self.relookups += 1
+                    seq += 1
+                    finishing.append((seq, ex.finish(a.q.table, a.cur, a.q.lookups, int(count)), a, extra))
+                    enqueued = progress = True
             if enqueued or len(done) == len(order):
                 continue
-            # nothing to enqueue: wait for the earliest outstanding fence, else the next arrival
-            fronts = [d[0][:2] for d in (steps, counting, gathering) if d]
+            # nothing to enqueue: wait for the earliest outstanding token, else the next arrival
+            fronts = [d[0][:2] for d in (steps, finishing) if d]
             if fronts:
                 ex.wait(min(fronts, key=lambda f: f[0])[1])
             elif nxt_arrival < len(order):
@@ -238,8 +256,9 @@ class Server:
 def run_serial(executor, queries: Sequence[Query], keep_values: bool = True,
                clock: Callable[[], float] = time.perf_counter,
                sleep: Callable[[float], None] = time.sleep) -> Dict[int, Result]:
-    """Serve the queries one at a time in arrival order, one scan launch per
-    predicate, waiting for each query's count and lookups before the next."""
+    """Serve the queries one at a time in arrival order with the plain per-query
+    calls: one scan launch per predicate, the row count read back to size the
+    lookup outputs, then the lookups; each query completes before the next starts."""
     order = sorted(queries, key=lambda q: (q.arrival, q.qid))
     t0 = clock()
     done = {}
@@ -254,11 +273,12 @@ def run_serial(executor, queries: Sequence[Query], keep_values: bool = True,
                 cur = executor.new_bv(q.table)
             executor.scan_step([(q.table, col, op, lo, hi, cur if k > 0 else None, nxt)])
             cur, nxt = nxt, cur
-        handle = executor.count_rows([(q.table, cur)])
-        executor.wait(handle)
-        count = int(executor.read_counts(handle)[0])
-        vals = {c: executor.lookup(q.table, c, cur, count) for c in q.lookups}
-        executor.wait(executor.fence())
+        tok = executor.finish(q.table, cur, [], 0)
+        executor.wait(tok)
+        count, _ = executor.result(tok)
+        tok = executor.finish(q.table, cur, q.lookups, int(count))
+        executor.wait(tok)
+        _, vals = executor.result(tok)
         done[q.qid] = Result(q.qid, count, vals if keep_values else {}, q.arrival, start, clock() - t0)
     return done
 
@@ -283,40 +303,48 @@ def poisson_arrivals(n: int, qps: float, seed: int) -> np.ndarray:
     return np.cumsum(rng.exponential(1.0 / qps, size=n))
 
 
-class _Counts:
-    __slots__ = ("host", "dev", "ev")
+class _Finish:
+    __slots__ = ("ev", "slot", "vals", "cap")
 
-    def __init__(self, host, dev, ev):
-        self.host, self.dev, self.ev = host, dev, ev
+    def __init__(self, ev, slot, vals, cap):
+        self.ev, self.slot, self.vals, self.cap = ev, slot, vals, cap   # vals: column -> output[cap]
 
 
 class GpuExecutor:
     """Executor over resident DeviceColumns: tables = {table: {column: DeviceColumn}}.
 
-    Scans run on the current stream; counts and lookups on a second stream
-    (default priority) that waits for the scans before them, so a finished
-    query's counting and gathering overlap the next scan step on the device.
+    Everything runs in order on one stream (the current stream at creation):
+    scans, then each finished query's compaction and lookups, so the device
+    serves queries in the order their work was enqueued and a lookup never
+    competes with a later query's scan.  Row counts come back through a pool of
+    pinned host slots filled by asynchronous copies.
     """
 
-    def __init__(self, tables, grid: int = 0, tiles_per_grab: int = 0):
+    def __init__(self, tables, grid: int = 0, tiles_per_grab: int = 0, slots: int = 1024):
         import torch
 
+        from . import _lib
         from . import column as C
 
         self.torch = torch
+        self.L = _lib
         self.C = C
         self.tables = tables
         self.grid = grid
         self.grab = tiles_per_grab
         self.main = torch.cuda.current_stream()
-        self.side = torch.cuda.Stream()
-        self._last_scan = None
         self._n = {}
         for t, cols in tables.items():
             ns = {int(dc.n_rows) for dc in cols.values()}
             if len(ns) != 1:
                 raise ValueError("table %s: columns of different lengths" % t)
             self._n[t] = ns.pop()
+        n_max = max(self._n.values()) if self._n else 0
+        self.ws = torch.empty(max(1, int(_lib.bst_compact_workspace_bytes(n_max))), dtype=torch.uint8, device="cuda")
+        self.ids = torch.empty(1, dtype=torch.int32, device="cuda")
+        self.dev_counts = torch.empty(slots, dtype=torch.int64, device="cuda")
+        self.host_counts = torch.empty(slots, dtype=torch.int64, pin_memory=True)
+        self.free = list(range(slots - 1, -1, -1))
 
     def n_rows(self, table):
         return self._n[table]
@@ -326,6 +354,22 @@ class GpuExecutor:
 
     def new_bv(self, table):
         return self.torch.empty(self.C.nwords(self._n[table]), dtype=self.torch.int64, device="cuda")
+
+    def _stream(self):
+        return self.main.cuda_stream
+
+    def _slot(self):
+        if not self.free:
+            raise RuntimeError("all %d count slots are in use" % self.dev_counts.numel())
+        return self.free.pop()
+
+    def _ids(self, cap):
+        # one staging array for the row IDs of every compaction: the work on the
+        # stream is ordered, so a finish's lookups have read it before the next
+        # compaction writes it
+        if self.ids.numel() < cap:
+            self.ids = self.torch.empty(cap, dtype=self.torch.int32, device="cuda")
+        return self.ids
 
     def scan_step(self, items):
         # enqueued only: the launch copies the batch's work list through the
@@ -346,34 +390,38 @@ class GpuExecutor:
                 b.close()
             ev = self.torch.cuda.Event()
             ev.record(self.main)
-        self._last_scan = ev
         return ev
 
-    def count_rows(self, pairs):
-        torch = self.torch
-        with torch.cuda.stream(self.side):
-            if self._last_scan is not None:
-                self.side.wait_event(self._last_scan)
-            cs = torch.cat([self.C.bv_popcount(bv, self._n[t]) for t, bv in pairs])
-            host = torch.empty(cs.shape, dtype=cs.dtype, pin_memory=True)
-            host.copy_(cs, non_blocking=True)
+    def finish(self, table, bv, columns, cap):
+        torch, L = self.torch, self.L
+        n = self._n[table]
+        slot = self._slot()
+        cnt = self.dev_counts[slot:slot + 1]
+        vals = {}
+        with torch.cuda.stream(self.main):
+            st = self._stream()
+            if columns and cap > 0:
+                ids = self._ids(cap)
+                L.bst_bv_compact(bv, n, ids, cap, cnt, self.ws, None, st)
+                for c in columns:
+                    v = torch.empty(cap, dtype=torch.int32, device="cuda")
+                    L.bst_lookup_counted(self.tables[table][c].h, ids, cnt, cap, v, None, st)
+                    vals[c] = v
+            else:
+                L.bst_bv_popcount(bv, n, cnt, st)
+                vals = {c: torch.empty(0, dtype=torch.int32, device="cuda") for c in columns}
+            self.host_counts[slot:slot + 1].copy_(cnt, non_blocking=True)
             ev = torch.cuda.Event()
-            ev.record(self.side)
-        return _Counts(host, cs, ev)
+            ev.record(self.main)
+        return _Finish(ev, slot, vals, cap)
 
-    def read_counts(self, handle):
-        handle.ev.synchronize()
-        return [int(v) for v in handle.host.tolist()]
-
-    def lookup(self, table, column, bv, count):
-        with self.torch.cuda.stream(self.side):
-            vals, _ = self.tables[table][column].lookup_bv(bv, max(int(count), 1))
-        return vals[: int(count)]
-
-    def fence(self):
-        ev = self.torch.cuda.Event()
-        ev.record(self.side)
-        return ev
+    def result(self, tok):
+        tok.ev.synchronize()
+        count = int(self.host_counts[tok.slot])
+        self.free.append(tok.slot)
+        if count > tok.cap and tok.vals:
+            return count, None
+        return count, {c: v[:count] for c, v in tok.vals.items()}
 
     def is_done(self, token):
         return getattr(token, "ev", token).query()
@@ -382,5 +430,5 @@ class GpuExecutor:
         getattr(token, "ev", token).synchronize()
 
     def sync(self):
-        """Make the current stream wait for the counts and lookups enqueued so far."""
-        self.torch.cuda.current_stream().wait_stream(self.side)
+        """Make the current stream wait for the work enqueued so far."""
+        self.torch.cuda.current_stream().wait_stream(self.main)

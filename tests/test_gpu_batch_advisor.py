@@ -132,6 +132,33 @@ def test_advisor_choice_consistent_with_oracle():
     assert all(np.all(t > 0) for t in res.times.values())
 
 
+def test_advisor_equality_profile_on_categorical_columns():
+    """Algorithm 5's '=' profile on a categorical column (codes of Algorithm 2):
+    the profiling literals are the oracle's, each layout's area is the trapezoid
+    sum of its own measured times, and the choice is the oracle's on those areas."""
+    from paper_2209_00220_amd.advisor import advise_column
+    from oracle.dictionary import build_dictionary
+
+    flush("advisor, '=' profile")
+    n = 1_500_000
+    x = datagen.zipf_column(n, 16, 1.2, seed=41)
+    count = 40
+    res = advise_column(x, numeric=False, width=16, layouts=("byteslice", "ppvbs_categorical"), repeats=3,
+                        count=count)
+    A, Q, _ = build_dictionary(x)
+    lits, sels = oadv.literals_eq(A, Q, count)
+    assert np.array_equal(res.lits, lits)
+    assert np.allclose(res.sels, sels, rtol=0, atol=1e-12)
+    for lay, t in res.times.items():
+        assert res.aucs[lay] == pytest.approx(oadv.auc(res.sels, t), rel=1e-9)
+        assert np.all(np.asarray(t) > 0)
+    want = oadv.choose({oadv.BYTESLICE: res.aucs["byteslice"], oadv.PPVBS: res.aucs["ppvbs_categorical"]})
+    assert res.chosen == ("byteslice" if want == oadv.BYTESLICE else "ppvbs_categorical")
+    for hc, dc in res.columns.values():
+        dc.close()
+        hc.close()
+
+
 def test_batches_back_to_back_without_waits():
     """Batches launched one after another with no host wait in between (their
     work lists go through the library's pinned staging ring, wrapping it at

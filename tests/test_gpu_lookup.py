@@ -183,3 +183,34 @@ def test_empty_column_every_entry_point():
             o.close()
         d0.close()
         d1.close()
+
+
+def test_lookup_counted_all_or_nothing():
+    """bst_lookup_counted looks up the compacted row IDs whose count stays on the
+    device: every value when the count fits the capacity, nothing (and the
+    overflow flag) when it does not."""
+    from paper_2209_00220_amd import _lib as L
+    from paper_2209_00220_amd.column import bv_compact, u32_to_numpy
+
+    n = 300_007
+    x = datagen.zipf_column(n, 16, 1.0, seed=71)
+    cols = device_columns(x, 16)
+    try:
+        for lay, (hc, col) in cols.items():
+            bv = col.scan("lt", 4000)
+            rows = np.nonzero(x < 4000)[0]
+            ids, count = bv_compact(bv, n, n)
+            for cap, fits in ((rows.shape[0], True), (rows.shape[0] + 17, True), (rows.shape[0] - 1, False)):
+                vals = torch.full((max(cap, 1),), -1, dtype=torch.int32, device="cuda")
+                status = torch.zeros(1, dtype=torch.int32, device="cuda")
+                L.bst_lookup_counted(col.h, ids, count, cap, vals, status, 0)
+                torch.cuda.synchronize()
+                got = u32_to_numpy(vals)
+                st = int(status.item())
+                if fits:
+                    assert st == 0 and np.array_equal(got[:rows.shape[0]], x[rows]), lay
+                    assert np.all(got[rows.shape[0]:] == 0xFFFFFFFF), lay
+                else:
+                    assert st & L.BST_DEV_OVERFLOW and np.all(got == 0xFFFFFFFF), lay
+    finally:
+        close_columns(cols)

@@ -67,6 +67,7 @@ CASES = [
     (150_000, 24, 0.0, datagen.SCATTER),    # uniform, K = 4
     (2_000_003, 20, 0.5, datagen.SORTED),   # K = 5
     (300_000, 32, 1.5, datagen.SCATTER),
+    (200_003, 4, 1.0, datagen.SCATTER),     # the sensitivity sweep's smallest domain
 ]
 
 
@@ -252,3 +253,33 @@ def test_scan_parity_many_tiles_per_wave(grid, gather):
     finally:
         L.bst_tune_set(L.TUNE_SCAN_GRID, saved[0])
         L.bst_tune_set(L.TUNE_GATHER_ROWS, saved[1])
+
+
+@pytest.mark.parametrize("w,sigma_exp", [(12, 0.25), (12, 0.5), (12, 0.75), (20, 0.25), (20, 0.5), (20, 0.75)])
+def test_gaussian_columns(w, sigma_exp):
+    """The sensitivity sweep's Gaussian inputs (mean at the domain's centre,
+    sigma = 2^(w/4), 2^(w/2), 2^(3w/4), rounded and clipped): every layout and
+    operator against the plain comparison, with and without an incoming mask."""
+    from paper_2209_00220_amd.column import bv_from_numpy
+
+    n = 150_001
+    sigma = 2.0 ** (w * sigma_exp)
+    flush("gaussian w=%d sigma=2^%.2f" % (w, w * sigma_exp))
+    x = datagen.gaussian_column(n, w, sigma, seed=31 * w + int(4 * sigma_exp))
+    A, _, _ = build_dictionary(x)
+    cols = device_columns(x, w)
+    mask_np = datagen.random_mask_words(n, seed=w + 5, density=0.5)
+    mask_t = bv_from_numpy(mask_np)
+    mask_rows = unpack_bits(mask_np, n)
+    lits = literal_set(A, w)
+    try:
+        for lay, (hc, col) in cols.items():
+            for op in OPS:
+                for i, lo in enumerate(lits):
+                    hi = lits[(i * 5 + 3) % len(lits)] if op == "between" else None
+                    for msk in (None, mask_t):
+                        got = _bv(col.scan(op, lo, hi, in_mask=msk))
+                        want = scan_values_bv(x, op, lo, hi, None if msk is None else mask_rows)
+                        assert np.array_equal(got, want), (lay, op, lo, hi, msk is not None)
+    finally:
+        close_columns(cols)

@@ -14,6 +14,7 @@ class HostExecutor:
     def __init__(self, tables, step_cost=0.0, clock=None):
         self.tables = tables
         self.steps = []
+        self.finishes = []
         self.step_cost = step_cost
         self.clock = clock
 
@@ -34,17 +35,14 @@ class HostExecutor:
             self.clock.t += self.step_cost
         return object()
 
-    def count_rows(self, pairs):
-        return [int(bv.sum()) for _, bv in pairs]
+    def finish(self, t, bv, columns, cap):
+        self.finishes.append((t, tuple(columns), cap))
+        count = int(bv.sum())
+        vals = {c: self.tables[t][c][bv].copy() for c in columns}
+        return (count, None if (columns and count > cap) else vals)
 
-    def read_counts(self, handle):
-        return handle
-
-    def lookup(self, t, c, bv, count):
-        return self.tables[t][c][bv].copy()
-
-    def fence(self):
-        return object()
+    def result(self, token):
+        return token
 
     def is_done(self, token):
         return True
@@ -140,7 +138,8 @@ def test_budget_limits_admission():
     qs = _queries(tables, 12, seed=5)
     per_query = 2 * 8 * ((5000 + 63) // 64)   # the larger table's two bitvectors
     ex = HostExecutor(tables)
-    srv = Server(ex, budget_bytes=6 * per_query)   # bitvectors may hold half: three queries
+    # no lookup outputs reserved up front: admission counts the bitvectors only
+    srv = Server(ex, budget_bytes=6 * per_query, lookup_cap_rows=0)   # reservations may hold half: three queries
     res = srv.run(qs)
     assert len(res) == len(qs)
     assert max(len(s) for s in ex.steps) <= 3
@@ -163,7 +162,8 @@ def test_lookups_keep_their_share_of_the_budget():
     per_query = 2 * 8 * ((5000 + 63) // 64)
     budget = 1 << 20
     ex = HostExecutor(tables, step_cost=0.01, clock=clock)
-    srv = Server(ex, budget_bytes=budget, scan_share=4 * per_query / budget, clock=clock, sleep=clock.sleep)
+    srv = Server(ex, budget_bytes=budget, scan_share=4 * per_query / budget, lookup_cap_rows=0, clock=clock,
+                 sleep=clock.sleep)
     res = srv.run(qs)
     assert len(qs) == 12 and max(len(s) for s in ex.steps) == 4 and len(ex.steps) == 3
     for q in qs:
@@ -240,15 +240,12 @@ class LazyExecutor(HostExecutor):
         self.max_scan_inflight = max(self.max_scan_inflight, inflight)
         return t
 
-    def count_rows(self, pairs):
-        return self._token(super().count_rows(pairs))
+    def finish(self, t, bv, columns, cap):
+        return self._token(super().finish(t, bv, columns, cap))
 
-    def read_counts(self, handle):
-        assert handle.done
-        return handle.value
-
-    def fence(self):
-        return self._token()
+    def result(self, token):
+        assert token.done
+        return token.value
 
     def is_done(self, token):
         return token.done
@@ -275,3 +272,34 @@ def test_scan_steps_in_flight_are_bounded(lookahead, lookahead_rows, bound):
         for c in q.lookups:
             assert np.array_equal(res[q.qid].values[c], want[c])
 
+
+
+def test_lookup_outputs_reserved_at_admission():
+    """A query reserves its bitvectors and the lookup outputs of up to
+    lookup_cap_rows rows when admitted; its lookups then follow its last scan
+    with no count read in between (one finish per query).  A query with more
+    rows looks up again with the exact count, and its result is unchanged."""
+    tables = _tables()
+    qs = _queries(tables, 30, seed=21)
+    for cap_rows, expect_relookup in ((1 << 25, False), (40, True)):
+        ex = HostExecutor(tables)
+        srv = Server(ex, budget_bytes=1 << 30, lookup_cap_rows=cap_rows)
+        res = srv.run(qs)
+        for q in qs:
+            want, cnt = _plain(tables, q)
+            assert res[q.qid].count == cnt
+            for c in q.lookups:
+                assert np.array_equal(res[q.qid].values[c], want[c])
+        big = sum(1 for q in qs if _plain(tables, q)[1] > cap_rows)
+        assert srv.relookups == big and (big > 0) == expect_relookup
+        assert len(ex.finishes) == len(qs) + big
+        assert all(cap == min(ex.n_rows(t), cap_rows) for t, cols, cap in ex.finishes[:1])
+        assert srv.in_use == 0 and srv.scan_in_use == 0
+    # the reservation limits admission: each query of table "a" reserves two
+    # bitvectors and 5000 rows of lookup outputs, so at most two fit at once
+    one = [q for q in qs if q.table == "a" and len(q.lookups) == 1][:6]
+    per = 2 * 8 * ((5000 + 63) // 64) + 4 * 5000 * 2
+    ex = HostExecutor(tables)
+    srv = Server(ex, budget_bytes=4 * per + 100, scan_share=0.5)
+    srv.run(one)
+    assert max(len(s) for s in ex.steps) <= 2 and srv.peak_in_use <= 4 * per + 100
