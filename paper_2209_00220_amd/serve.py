@@ -150,6 +150,7 @@ class Server:
             if not q.preds:
                 raise ValueError("query %d has no predicate" % q.qid)
         ex = self.ex
+        release = getattr(ex, "release", lambda tok: None)   # optional: a retired step token
         t0 = self.clock()
         nxt_arrival = 0
         waiting: collections.deque = collections.deque()
@@ -179,7 +180,9 @@ class Server:
             enqueued = False
             # one scan step: the next predicate of the oldest scanning queries, one launch
             while steps and ex.is_done(steps[0][1]):
-                inflight_rows -= steps.popleft()[2]
+                _, tok, r = steps.popleft()
+                inflight_rows -= r
+                release(tok)
             batch, rows = [], 0
             if scanning and len(steps) < self.lookahead:
                 for a in scanning:
@@ -345,6 +348,20 @@ class GpuExecutor:
         self.dev_counts = torch.empty(slots, dtype=torch.int64, device="cuda")
         self.host_counts = torch.empty(slots, dtype=torch.int64, pin_memory=True)
         self.free = list(range(slots - 1, -1, -1))
+        self.events = []   # recorded events whose tokens are done, for reuse
+
+    def _event(self):
+        ev = self.events.pop() if self.events else self.torch.cuda.Event()
+        ev.record(self.main)
+        return ev
+
+    def _on_main(self):
+        """The scan stream as the current stream (a no-op when it already is)."""
+        import contextlib
+
+        if self.torch.cuda.current_stream() == self.main:
+            return contextlib.nullcontext()
+        return self.torch.cuda.stream(self.main)
 
     def n_rows(self, table):
         return self._n[table]
@@ -380,17 +397,15 @@ class GpuExecutor:
 
         specs = [(self.tables[t][c], op, lo, hi, inb) for t, c, op, lo, hi, inb, _ in items]
         outs = [it[6] for it in items]
-        with self.torch.cuda.stream(self.main):
+        with self._on_main():
             if len(items) == 1:
                 dc, op, lo, hi, inb = specs[0]
-                dc.scan(op, lo, hi, in_mask=inb, out=outs[0])
+                dc.scan(op, lo, hi, in_mask=inb, out=outs[0], stream=self.main)
             else:
                 b = Batch(specs, outs)
-                b.launch(self.grid, self.grab, use_graph=False)
+                b.launch(self.grid, self.grab, use_graph=False, stream=self.main)
                 b.close()
-            ev = self.torch.cuda.Event()
-            ev.record(self.main)
-        return ev
+            return self._event()
 
     def finish(self, table, bv, columns, cap):
         torch, L = self.torch, self.L
@@ -398,7 +413,7 @@ class GpuExecutor:
         slot = self._slot()
         cnt = self.dev_counts[slot:slot + 1]
         vals = {}
-        with torch.cuda.stream(self.main):
+        with self._on_main():
             st = self._stream()
             if columns and cap > 0:
                 ids = self._ids(cap)
@@ -411,17 +426,21 @@ class GpuExecutor:
                 L.bst_bv_popcount(bv, n, cnt, st)
                 vals = {c: torch.empty(0, dtype=torch.int32, device="cuda") for c in columns}
             self.host_counts[slot:slot + 1].copy_(cnt, non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(self.main)
+            ev = self._event()
         return _Finish(ev, slot, vals, cap)
 
     def result(self, tok):
         tok.ev.synchronize()
         count = int(self.host_counts[tok.slot])
         self.free.append(tok.slot)
+        self.events.append(tok.ev)
         if count > tok.cap and tok.vals:
             return count, None
         return count, {c: v[:count] for c, v in tok.vals.items()}
+
+    def release(self, token):
+        """A scan-step token the server no longer needs: its event is reused."""
+        self.events.append(token)
 
     def is_done(self, token):
         return getattr(token, "ev", token).query()
