@@ -545,6 +545,13 @@ def wide_main(args):
     print(json.dumps(out), flush=True)
 
 
+def _grab_name(grab):
+    """tiles_per_grab as reported: a number, or "round robin"."""
+    from paper_2209_00220_amd import _lib as L
+
+    return "round robin" if grab == L.BATCH_ROUND_ROBIN else grab
+
+
 def batch_main(args):
     """Many scans over many columns: one persistent launch (HIP graph, autotuned
     shape) against one launch per predicate."""
@@ -553,6 +560,7 @@ def batch_main(args):
 
     import datagen
     from datagen import workloads
+    from paper_2209_00220_amd import _lib as L
     from paper_2209_00220_amd.batch import Batch, autotune, time_call
     from paper_2209_00220_amd.column import DeviceColumn, Dictionary, HostColumn, bv_popcount
 
@@ -590,7 +598,9 @@ def batch_main(args):
     single_ms = _ms_events(singles)
     b = Batch([(cols[c], op, lo, hi, None) for c, op, lo, hi, _ in preds], outs)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    best, table = autotune(b, grids=[cus * 2, cus * 3, cus * 4, cus * 8], grabs=(8, 16, 32, 64), repeats=3)
+    best, table = autotune(b, grids=[cus * 2, cus * 3, cus * 4, cus * 8], grabs=(8, 16, 32, 64, L.BATCH_ROUND_ROBIN),
+                           streams=args.batch_streams, repeats=3)
+    one_stream = min(v for k, v in table.items() if k[2] == 1) if 1 in args.batch_streams else None
     batch_ms = time_call(lambda: b.launch(best[0], best[1], True), repeats=5)
     torch.cuda.synchronize()
     # every result's popcount against the plain count from the value counts
@@ -613,7 +623,8 @@ def batch_main(args):
                                "%d predicates (<, <=, =, BETWEEN; selectivity log-uniform 0.01-50%%)"
                                % (len(specs), len(preds)), "rows_scanned": rows},
         "batch_ms": round(batch_ms, 3), "single_launches_ms": round(single_ms, 3),
-        "speedup": round(single_ms / batch_ms, 3), "grid": best[0], "tiles_per_grab": best[1],
+        "speedup": round(single_ms / batch_ms, 3), "grid": best[0], "tiles_per_grab": _grab_name(best[1]), "streams": best[2],
+        "one_stream_ms": None if one_stream is None else round(one_stream, 3),
         "alg_bytes": alg, "batch_hbm_frac": round(alg / (batch_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "single_gtuples": round(rows / (single_ms * 1e-3) / 1e9, 1),
     }
@@ -780,6 +791,8 @@ def main():
     ap.add_argument("--wide-rows", type=int, default=100_000_000)
     ap.add_argument("--batch-cols", type=int, default=64)
     ap.add_argument("--batch-preds", type=int, default=256)
+    ap.add_argument("--batch-streams", type=lambda v: tuple(int(x) for x in v.split(",")), default=(1, 2, 4),
+                    help="stream counts the batch autotuner tries (comma-separated, each 1..4)")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--rows", type=int, default=500_000_000)
@@ -1008,6 +1021,7 @@ def main():
             "-" if res[lay]["lookup_mrows"] is None else "%.0f" % res[lay]["lookup_mrows"]))
     if args.batch:
         # the same step's scans as one persistent launch (replayed from a HIP graph)
+        from paper_2209_00220_amd import _lib as L
         from paper_2209_00220_amd.batch import Batch, autotune, time_call
 
         progress("batched form: %d scans in one launch" % (len(layouts) * len(preds)))
@@ -1015,10 +1029,11 @@ def main():
         outs = [cols[layouts[0]][1].new_bv() for _ in specs]
         b = Batch(specs, outs)
         cus = torch.cuda.get_device_properties(0).multi_processor_count
-        best, table = autotune(b, grids=[cus * 2, cus * 3, cus * 4, cus * 8], grabs=(8, 16, 32, 64), repeats=3)
+        best, table = autotune(b, grids=[cus * 2, cus * 3, cus * 4, cus * 8], grabs=(8, 16, 32, 64, L.BATCH_ROUND_ROBIN),
+                               streams=args.batch_streams, repeats=3)
         batch_ms = time_call(lambda: b.launch(best[0], best[1], True), repeats=5)
         single_ms = float(sum(sum(res[lay]["scan_ms"]) for lay in layouts))
-        out["batch"] = {"scans": len(specs), "grid": best[0], "tiles_per_grab": best[1],
+        out["batch"] = {"scans": len(specs), "grid": best[0], "tiles_per_grab": _grab_name(best[1]), "streams": best[2],
                         "batch_ms": round(batch_ms, 3), "single_launches_ms": round(single_ms, 3),
                         "batch_gtuples": round(n * len(specs) / (batch_ms * 1e-3) / 1e9, 1)}
         progress("batch: %s" % json.dumps(out["batch"]))

@@ -79,6 +79,7 @@ typedef struct {
 
 #define BST_KMAX 6          /* longest PP-VBS code in bytes (2 levels + 4-byte leaf) */
 #define BST_TILE_ROWS 2048  /* rows per tile of the device layouts                   */
+#define BST_BATCH_ROUND_ROBIN 0xFFFFFFFFu /* tiles_per_grab: static round-robin tiles */
 
 /* Device buffer slots of a stored column (bst_column_info.bytes[slot]). */
 enum {
@@ -342,10 +343,19 @@ int bst_batch_prepare(const bst_column* const* cols, const bst_pred* preds,
  * `tiles_per_grab` (0 = tuned default) consecutive 2048-row tiles at a time
  * from the group's queue -- more when the group is large, so that a wave takes
  * about four times per group; a group too small to give every wave
- * `tiles_per_grab` tiles is spread evenly over its waves instead.  With use_graph != 0 the launch
- * sequence is captured once into a HIP graph and replayed on later calls with
- * the same grid and grab size.  Errors: BST_EINVAL for a NULL batch, BST_EHIP
- * for a failed launch or capture.
+ * `tiles_per_grab` tiles is spread evenly over its waves instead.
+ * tiles_per_grab = BST_BATCH_ROUND_ROBIN takes no counter: the group's tiles
+ * (its items' tiles concatenated) go round robin over the launch's waves, so
+ * each item is read as a single-column scan reads it.  With
+ * BST_TUNE_BATCH_STREAMS = s > 1 the groups are spread over s streams (largest
+ * group first, to the least loaded): helper streams of the library fork off
+ * `stream` after the counter reset and join back into it before the call
+ * returns, so later work on `stream` still sees every result.  The items must
+ * be independent (no item's incoming mask is another item's output).  With
+ * use_graph != 0 the launch sequence is captured once into a HIP graph (the
+ * streams become parallel branches) and replayed on later calls with the same
+ * grid, grab size and stream count.  Errors: BST_EINVAL for a NULL batch,
+ * BST_EHIP for a failed launch or capture.
  */
 int bst_batch_launch(bst_batch* b, uint32_t grid, uint32_t tiles_per_grab, int use_graph,
                      void* stream);
@@ -361,7 +371,10 @@ enum {
                                   later bytes a scan gathers one by one; a tile with
                                   a lane holding more copies the level's run of the
                                   slice into LDS with one read instead                */
-    BST_TUNE_NKEYS = 5
+    BST_TUNE_BATCH_STREAMS = 5,/* streams a batch's groups are spread over (1..4,
+                                  default 1): the caller's stream and library-owned
+                                  helper streams forked from it and joined back   */
+    BST_TUNE_NKEYS = 6
 };
 int bst_tune_set(int key, int64_t value);
 int64_t bst_tune_get(int key);

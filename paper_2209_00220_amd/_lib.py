@@ -25,9 +25,10 @@ LT, LE, GT, GE, EQ, NE, BETWEEN = range(7)
 OP_CODES = {"lt": LT, "le": LE, "gt": GT, "ge": GE, "eq": EQ, "ne": NE, "between": BETWEEN}
 KMAX = 6
 TILE_ROWS = 2048
+BATCH_ROUND_ROBIN = 0xFFFFFFFF   # tiles_per_grab: static round-robin tiles, no counter
 NBUF = 19
 BUF_BS1, BUF_BS2, BUF_M2, BUF_DIR2, BUF_PACKED, BUF_DICT, BUF_TRIE = 0, 1, 6, 11, 16, 17, 18
-TUNE_SCAN_GRID, TUNE_LOOKUP_GRID, TUNE_BATCH_GRID, TUNE_BATCH_GRAB, TUNE_GATHER_ROWS = 0, 1, 2, 3, 4
+TUNE_SCAN_GRID, TUNE_LOOKUP_GRID, TUNE_BATCH_GRID, TUNE_BATCH_GRAB, TUNE_GATHER_ROWS, TUNE_BATCH_STREAMS = 0, 1, 2, 3, 4, 5
 
 
 class BstError(RuntimeError):

@@ -67,20 +67,29 @@ def time_call(fn, repeats: int = 5, warmup: int = 1, stream=None) -> float:
     return float(np.median(samples))
 
 
-def autotune(batch: Batch, grids=None, grabs=(1, 2, 4, 8, 16), repeats: int = 5, use_graph: bool = True):
-    """Time every (grid, tiles_per_grab) pair and return the fastest with all timings.
+def autotune(batch: Batch, grids=None, grabs=(1, 2, 4, 8, 16), streams=(1,), repeats: int = 5,
+             use_graph: bool = True):
+    """Time every (grid, tiles_per_grab, streams) triple and return the fastest
+    with all timings.  streams: how many streams the batch's groups are spread
+    over (1..4).
 
-    The chosen pair is also stored as the library's default batch shape.
+    The chosen triple is also stored as the library's default batch shape.
     """
     if grids is None:
         cus = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
         grids = [cus * k for k in (2, 4, 8, 16)]
     results = {}
-    for g, t in itertools.product(grids, grabs):
-        results[(g, t)] = time_call(lambda: batch.launch(g, t, use_graph), repeats=repeats)
+    saved = L.bst_tune_get(L.TUNE_BATCH_STREAMS)
+    try:
+        for s, g, t in itertools.product(streams, grids, grabs):
+            L.bst_tune_set(L.TUNE_BATCH_STREAMS, s)
+            results[(g, t, s)] = time_call(lambda: batch.launch(g, t, use_graph), repeats=repeats)
+    finally:
+        L.bst_tune_set(L.TUNE_BATCH_STREAMS, saved)
     best = min(results, key=results.get)
     L.bst_tune_set(L.TUNE_BATCH_GRID, best[0])
     L.bst_tune_set(L.TUNE_BATCH_GRAB, best[1])
+    L.bst_tune_set(L.TUNE_BATCH_STREAMS, best[2])
     return best, results
 
 

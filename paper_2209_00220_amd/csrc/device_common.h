@@ -2,12 +2,15 @@
 // Device code shared by the gfx950 kernels of the ByteStore library.
 //
 // Device layouts (built by host_encode.cpp), all in tiles of 2048 rows:
-//  * tile-interleaved slices (BS_1 of PP-VBS and ByteSlice, every ByteSlice
-//    slice): lane L of a wave owns the 32 consecutive rows t*2048 + 32L + p
-//    (p = 0..31) of tile t, held as eight dwords; row p is byte p / 8 of dword
-//    p % 8, dwords 0-3 at t*2048 + 16L and dwords 4-7 at t*2048 + 1024 + 16L
-//    (slice_pos()).  Two 16-byte loads per lane bring a tile in, each covering
-//    1 KB contiguously, and a lane's 32 outcome bits form its result dword.
+//  * tile-interleaved slices (BS_1 of PP-VBS and ByteSlice): lane L of a wave
+//    owns the 32 consecutive rows t*2048 + 32L + p (p = 0..31) of tile t, held
+//    as eight dwords; row p is byte p / 8 of dword p % 8, dwords 0-3 at
+//    t*2048 + 16L and dwords 4-7 at t*2048 + 1024 + 16L (slice_pos()).  Two
+//    16-byte loads per lane bring a tile in, each covering 1 KB contiguously,
+//    and a lane's 32 outcome bits form its result dword.
+//  * ByteSlice slices after the first: the same eight dwords per lane, stored
+//    contiguously at t*2048 + 32L (lane_slice_pos()), since only lanes with
+//    rows still pending read them.
 //  * PP-VBS BS_j (j >= 2) compacted in row order (only rows with a j-th byte),
 //    bitmask M_j one uint64 per 64 rows, directory DIR_j = running count of
 //    j-th bytes every 2^dir_shift rows.
@@ -84,6 +87,13 @@ __device__ __forceinline__ uint64_t valid_mask(uint64_t word, uint64_t n) {
 __device__ __forceinline__ uint64_t slice_pos(uint64_t r) {
     const uint32_t p = (uint32_t)r & 31, lane = (uint32_t)(r >> 5) & 63, i = p & 7;
     return (r & ~(uint64_t)(kTileRows - 1)) + (i >> 2) * 1024 + lane * 16 + (i & 3) * 4 + (p >> 3);
+}
+
+// Byte offset of row r in a ByteSlice slice after the first: the same rows per
+// lane and bytes per dword, each lane's 32 bytes contiguous at 32L.
+__device__ __forceinline__ uint64_t lane_slice_pos(uint64_t r) {
+    const uint32_t p = (uint32_t)r & 31, lane = (uint32_t)(r >> 5) & 63;
+    return (r & ~(uint64_t)(kTileRows - 1)) + lane * 32 + (p & 7) * 4 + (p >> 3);
 }
 
 struct Stats {
@@ -286,7 +296,8 @@ __device__ __forceinline__ uint32_t lookup_row(const DevCol& c, uint64_t r) {
     }
     if (c.layout == BST_BYTESLICE) {
         uint64_t v = c.bs[1][pos1];
-        for (uint32_t j = 2; j <= c.K; ++j) v = (v << 8) | c.bs[j][pos1];
+        const uint64_t posj = lane_slice_pos(r);
+        for (uint32_t j = 2; j <= c.K; ++j) v = (v << 8) | c.bs[j][posj];
         const uint32_t code = (uint32_t)(v >> (8 * c.K - c.width));
         return c.domain_mode ? code : c.dict[code];
     }

@@ -239,6 +239,14 @@ static inline uint64_t bs1_pos(uint64_t r) {
     return (r & ~(uint64_t)(kTileRows - 1)) + (i >> 2) * 1024 + lane * 16 + (i & 3) * 4 + (p >> 3);
 }
 
+static inline uint64_t bsj_pos(uint64_t r) {
+    // ByteSlice slices after the first: lane L = (r / 32) % 64 of a tile owns its
+    // 32 rows as 32 contiguous bytes at 32L (row p = r % 32 in byte p / 8 of dword
+    // p % 8), so a lane that needs its bytes of the slice reads one 32-byte span
+    const uint64_t p = r & 31, lane = (r >> 5) & 63;
+    return (r & ~(uint64_t)(kTileRows - 1)) + lane * 32 + (p & 7) * 4 + (p >> 3);
+}
+
 static int log2_exact(uint32_t v) {
     int s = 0;
     while ((1u << s) < v) ++s;
@@ -302,8 +310,8 @@ static void build_vbs(HostColumn& c, const uint32_t* rank, uint32_t T) {
     }
 }
 
-// ByteSlice: code left-aligned in K bytes; every slice tile-interleaved like
-// PP-VBS's BS_1.
+// ByteSlice: code left-aligned in K bytes; BS_1 tile-interleaved like PP-VBS's
+// BS_1, later slices with each lane's 32 bytes contiguous (bsj_pos).
 static void build_byteslice(HostColumn& c, const uint32_t* vals, uint32_t T) {
     const uint64_t n = c.n, npad = c.ntiles * kTileRows;
     const uint32_t K = c.K, w = c.width;
@@ -312,11 +320,12 @@ static void build_byteslice(HostColumn& c, const uint32_t* vals, uint32_t T) {
     parallel_chunks(n, T, kTileRows, [&](uint64_t lo, uint64_t hi, uint32_t) {
         for (uint64_t r = lo; r < hi; ++r) {
             uint64_t v = (uint64_t)vals[r] << (8 * K - w);
-            // every slice tile-interleaved like BS_1, so a tile's byte j comes into
-            // registers in the same lane layout as its byte 1
-            const uint64_t pos = bs1_pos(r);
-            c.buf[BST_BUF_BS1][pos] = (uint8_t)(v >> (8 * (K - 1)));
-            for (uint32_t j = 2; j <= K; ++j) c.buf[BST_BUF_BS2 + j - 2][pos] = (uint8_t)(v >> (8 * (K - j)));
+            // every slice holds a lane's 32 rows in the same registers as BS_1; later
+            // slices keep each lane's bytes together (read lane by lane, only by
+            // lanes with rows still pending)
+            c.buf[BST_BUF_BS1][bs1_pos(r)] = (uint8_t)(v >> (8 * (K - 1)));
+            const uint64_t pj = bsj_pos(r);
+            for (uint32_t j = 2; j <= K; ++j) c.buf[BST_BUF_BS2 + j - 2][pj] = (uint8_t)(v >> (8 * (K - j)));
         }
     });
 }
@@ -778,8 +787,10 @@ int bst_host_paper_view(const bst_host_column* hc, int part, int j, void* out, u
         if (!out) return BST_OK;
         uint8_t* o = (uint8_t*)out;
         const uint8_t* src = c.buf[j == 1 ? BST_BUF_BS1 : BST_BUF_BS2 + j - 2].data();
-        if (j == 1 || c.layout == BST_BYTESLICE)   // tile-interleaved slices back to row order
+        if (j == 1)   // tile-interleaved slices back to row order
             for (uint64_t r = 0; r < n; ++r) o[r] = src[bs1_pos(r)];
+        else if (c.layout == BST_BYTESLICE)
+            for (uint64_t r = 0; r < n; ++r) o[r] = src[bsj_pos(r)];
         else
             memcpy(o, src, len);
         return BST_OK;

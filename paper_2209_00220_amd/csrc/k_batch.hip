@@ -1,4 +1,5 @@
 // Batched scans: many predicates over many columns in one persistent launch.
+#include <algorithm>
 #include <deque>
 #include <mutex>
 #include <vector>
@@ -30,14 +31,16 @@ static BatchKernel batch_kernel(uint32_t kind, bool has_in) {
         const bool dense = kind & 1;
         const int mi = (kind >> 1) & 3;
         if (kind & 8) return batch_short_kernel(mi, dense, has_in);
-#define BST_K(MODE)                                                                                        \
-    return dense ? (has_in ? k_batch_slices<MODE, -1, true, true> : k_batch_slices<MODE, -1, true, false>) \
-                 : (has_in ? k_batch_slices<MODE, -1, false, true> : k_batch_slices<MODE, -1, false, false>)
+        // a '<', '>' or '=' literal that is not one byte is longer (SHORT = 0); a
+        // BETWEEN may have one short bound, decided per item (SHORT = -1)
+#define BST_K(MODE, SH)                                                                                    \
+    return dense ? (has_in ? k_batch_slices<MODE, SH, true, true> : k_batch_slices<MODE, SH, true, false>) \
+                 : (has_in ? k_batch_slices<MODE, SH, false, true> : k_batch_slices<MODE, SH, false, false>)
         switch (mi) {
-            case 0: BST_K(kModeLT);
-            case 1: BST_K(kModeGT);
-            case 2: BST_K(kModeEQ);
-            default: BST_K(kModeBetween);
+            case 0: BST_K(kModeLT, 0);
+            case 1: BST_K(kModeGT, 0);
+            case 2: BST_K(kModeEQ, 0);
+            default: BST_K(kModeBetween, -1);
         }
 #undef BST_K
     }
@@ -138,6 +141,44 @@ int ring_upload(void* dst, const void* src, size_t len, hipStream_t st) {
     return BST_OK;
 }
 
+// Streams on which a batch's groups run side by side, per device: the caller's
+// stream plus up to kBatchStreamsMax - 1 helpers (default priority, created
+// on first use and kept until the process ends), with the events that fork
+// the helpers off the caller's stream and join them back.  Under graph
+// capture the fork and join become edges of the graph, so the groups are
+// parallel branches of it.
+constexpr int kBatchStreamsMax = 4;
+constexpr int kMaxDevices = 64;
+
+struct ForkSet {
+    hipStream_t helper[kBatchStreamsMax - 1] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kBatchStreamsMax - 1] = {};
+    bool ready = false;
+};
+
+int fork_set(ForkSet** out) {
+    static std::mutex mu;
+    static ForkSet sets[kMaxDevices];
+    int dev = 0;
+    int rc = hip_check(hipGetDevice(&dev), "batch streams");
+    if (rc) return rc;
+    if (dev < 0 || dev >= kMaxDevices) return set_error(BST_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(mu);
+    ForkSet& f = sets[dev];
+    if (!f.ready) {
+        rc = hip_check(hipEventCreateWithFlags(&f.fork, hipEventDisableTiming), "batch fork event");
+        for (int i = 0; !rc && i < kBatchStreamsMax - 1; ++i) {
+            rc = hip_check(hipStreamCreateWithFlags(&f.helper[i], hipStreamNonBlocking), "batch helper stream");
+            if (!rc) rc = hip_check(hipEventCreateWithFlags(&f.join[i], hipEventDisableTiming), "batch join event");
+        }
+        if (rc) return rc;   // a partly built set is completed on the next call
+        f.ready = true;
+    }
+    *out = &f;
+    return BST_OK;
+}
+
 }  // namespace
 
 struct BatchGroup {
@@ -157,6 +198,7 @@ struct bst_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint32_t graph_grid = 0, graph_grab = 0;
+    int64_t graph_streams = 0;
     hipStream_t graph_stream = nullptr;
 };
 
@@ -246,30 +288,65 @@ static int batch_enqueue(bst_batch* b, uint32_t grid, uint32_t grab, hipStream_t
         int rc = enqueue_fill(b->fills[i].first, b->fills[i].second.first, b->fill_rows[i], b->fills[i].second.second, st);
         if (rc) return rc;
     }
-    if (!b->groups.empty()) {
-        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(128), 0, st, ws, (int)b->groups.size());
-        for (size_t g = 0; g < b->groups.size(); ++g) {
-            const BatchGroup& gr = b->groups[g];
-            char* h = ws + g * kBatchHeaderBytes;
-            // no more waves than the group has tiles
-            const uint32_t grid_g = (uint32_t)std::max<uint64_t>(
-                1, std::min<uint64_t>(grid, (gr.tiles + kWavesPerBlock - 1) / kWavesPerBlock));
-            const uint64_t waves = (uint64_t)grid_g * kWavesPerBlock;
-            // A small group spreads over all its waves, one take each.  A large one
-            // takes at least `grab` tiles at a time and no more than about four
-            // takes per wave: every take is an atomic on the group's one counter.
-            uint64_t take;
-            if (gr.tiles <= (uint64_t)grab * waves)
-                take = std::max<uint64_t>(1, (gr.tiles + waves - 1) / waves);
-            else
-                take = std::max<uint64_t>(grab, (gr.tiles + 4 * waves - 1) / (4 * waves));
-            take = std::min<uint64_t>(take, 1u << 20);
-            hipLaunchKernelGGL(batch_kernel(gr.kind, gr.has_in), dim3(grid_g), dim3(kBlock), 0, st,
-                               (const BatchHeader*)h, items + gr.first, (unsigned long long*)(h + 32),
-                               (uint32_t)take);
+    if (b->groups.empty()) return hip_check(hipGetLastError(), "batch launch");
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(128), 0, st, ws, (int)b->groups.size());
+    // Groups go to the least loaded of `ns` streams, largest first: a small group
+    // that cannot fill the chip, and the tail of each launch, overlap with other
+    // groups instead of idling the device.
+    const int ns = (int)std::min<uint64_t>(b->groups.size(),
+                                           std::max<int64_t>(1, std::min<int64_t>(g_tune[BST_TUNE_BATCH_STREAMS],
+                                                                                  kBatchStreamsMax)));
+    ForkSet* fs = nullptr;
+    hipStream_t lanes[kBatchStreamsMax] = {st};
+    if (ns > 1) {
+        int rc = fork_set(&fs);
+        if (!rc) rc = hip_check(hipEventRecord(fs->fork, st), "batch fork");
+        for (int i = 1; !rc && i < ns; ++i) {
+            lanes[i] = fs->helper[i - 1];
+            rc = hip_check(hipStreamWaitEvent(lanes[i], fs->fork, 0), "batch fork");
         }
+        if (rc) return rc;
     }
-    return hip_check(hipGetLastError(), "batch launch");
+    std::vector<uint32_t> order(b->groups.size());
+    for (size_t g = 0; g < order.size(); ++g) order[g] = (uint32_t)g;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return b->groups[x].tiles > b->groups[y].tiles; });
+    uint64_t load[kBatchStreamsMax] = {};
+    for (uint32_t g : order) {
+        const BatchGroup& gr = b->groups[g];
+        int lane = 0;
+        for (int i = 1; i < ns; ++i)
+            if (load[i] < load[lane]) lane = i;
+        load[lane] += gr.tiles;
+        const hipStream_t gs = lanes[lane];
+        char* h = ws + g * kBatchHeaderBytes;
+        // no more waves than the group has tiles
+        const uint32_t grid_g = (uint32_t)std::max<uint64_t>(
+            1, std::min<uint64_t>(grid, (gr.tiles + kWavesPerBlock - 1) / kWavesPerBlock));
+        const uint64_t waves = (uint64_t)grid_g * kWavesPerBlock;
+        // A small group spreads over all its waves, one take each.  A large one
+        // takes at least `grab` tiles at a time and no more than about four
+        // takes per wave: every take is an atomic on the group's one counter.
+        // Round robin passes 0.
+        uint64_t take;
+        if (grab == BST_BATCH_ROUND_ROBIN)
+            take = 0;
+        else if (gr.tiles <= (uint64_t)grab * waves)
+            take = std::max<uint64_t>(1, (gr.tiles + waves - 1) / waves);
+        else
+            take = std::max<uint64_t>(grab, (gr.tiles + 4 * waves - 1) / (4 * waves));
+        if (take) take = std::min<uint64_t>(take, 1u << 20);
+        hipLaunchKernelGGL(batch_kernel(gr.kind, gr.has_in), dim3(grid_g), dim3(kBlock), 0, gs,
+                           (const BatchHeader*)h, items + gr.first, (unsigned long long*)(h + 32),
+                           (uint32_t)take);
+    }
+    int rc = hip_check(hipGetLastError(), "batch launch");
+    for (int i = 1; i < ns; ++i) {   // join every helper back, also after an error
+        int r2 = hip_check(hipEventRecord(fs->join[i - 1], lanes[i]), "batch join");
+        if (!r2) r2 = hip_check(hipStreamWaitEvent(st, fs->join[i - 1], 0), "batch join");
+        if (!rc) rc = r2;
+    }
+    return rc;
 }
 
 int bst_batch_launch(bst_batch* b, uint32_t grid, uint32_t tiles_per_grab, int use_graph, void* stream) {
@@ -291,7 +368,8 @@ int bst_batch_launch(bst_batch* b, uint32_t grid, uint32_t tiles_per_grab, int u
         b->uploaded = true;
     }
     if (!use_graph) return batch_enqueue(b, grid, tiles_per_grab, st);
-    if (!b->exec || b->graph_grid != grid || b->graph_grab != tiles_per_grab) {
+    if (!b->exec || b->graph_grid != grid || b->graph_grab != tiles_per_grab ||
+        b->graph_streams != g_tune[BST_TUNE_BATCH_STREAMS]) {
         if (b->exec) hipGraphExecDestroy(b->exec);
         if (b->graph) hipGraphDestroy(b->graph);
         b->exec = nullptr;
@@ -310,6 +388,7 @@ int bst_batch_launch(bst_batch* b, uint32_t grid, uint32_t tiles_per_grab, int u
         if (rc) return rc;
         b->graph_grid = grid;
         b->graph_grab = tiles_per_grab;
+        b->graph_streams = g_tune[BST_TUNE_BATCH_STREAMS];
     }
     return hip_check(hipGraphLaunch(b->exec, st), "graph launch");
 }

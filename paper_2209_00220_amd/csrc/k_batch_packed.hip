@@ -10,18 +10,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_packed(const BatchHeader* __re
                                                          const BatchItem* __restrict__ items,
                                                          unsigned long long* __restrict__ counter, uint32_t grab) {
     const uint32_t lane = threadIdx.x & 63;
-    const uint64_t total = hdr->total_tiles;
-    const uint32_t n_items = hdr->n_items;
     uint64_t alg = 0;
-    for (uint64_t start = batch_first_take(grab); start < total;
-         start = batch_next_take(counter, grab, total, lane)) {
-        const uint64_t stop = std::min<uint64_t>(total, start + grab);
-        for (uint32_t cur = batch_find(items, n_items, start); cur < n_items && items[cur].tile0 < stop; ++cur) {
-            const BatchItem& it = items[cur];
-            const uint64_t b0 = std::max<uint64_t>(start, it.tile0) - it.tile0;
-            const uint64_t b1 = std::min<uint64_t>(stop, it.tile0 + it.c.ntiles) - it.tile0;
-            scan_packed_range<W, HAS_IN>(it.c, it.pl, it.in_mask, it.out, b0, b1, 1, lane, alg);
-        }
+    BatchSegments seg(hdr, items, counter, grab, lane);
+    uint32_t i;
+    uint64_t b0, b1, stride;
+    while (seg.next(i, b0, b1, stride)) {
+        const BatchItem& it = items[uniform(i)];
+        scan_packed_range<W, HAS_IN>(it.c, it.pl, it.in_mask, it.out, b0, b1, stride, lane, alg);
     }
 }
 

@@ -214,7 +214,7 @@ DeviceProps& props() {
     return p;
 }
 
-int64_t g_tune[BST_TUNE_NKEYS] = {0, 0, 0, 16, 4};
+int64_t g_tune[BST_TUNE_NKEYS] = {0, 0, 0, 16, 4, 1};
 
 PackedLit packed_literal(const HostColumn& h, const ScanLit& s) {
     PackedLit p{0, 0, (uint32_t)s.negate, 0};
@@ -608,6 +608,8 @@ int bst_advise(const bst_column* const* cands, int n_cand, int op, const uint32_
 
 int bst_tune_set(int key, int64_t value) {
     if (key < 0 || key >= BST_TUNE_NKEYS) return set_error(BST_EINVAL, "bad tuning key");
+    if (key == BST_TUNE_BATCH_STREAMS && (value < 1 || value > 4))
+        return set_error(BST_EINVAL, "batch streams must be 1..4");
     g_tune[key] = value;
     return BST_OK;
 }

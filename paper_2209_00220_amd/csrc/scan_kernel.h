@@ -7,18 +7,6 @@
 namespace bst {
 namespace dev {
 
-// Waves per SIMD the variant is built for: 8 (64 VGPRs) where a tile's work
-// ends with its byte-1 pass; variants that keep a tile's later-byte reads in
-// flight (two tiles' gathered bytes or dense slice bytes besides two tiles'
-// loads), and BETWEEN with its two literals, are built for 7 (73 VGPRs);
-// ByteSlice BETWEEN with a multi-byte literal, whose tile state holds a lane's
-// 32 bytes of the second slice, for 6 (85 VGPRs).
-template <int MODE, int SHORT, bool DENSE>
-constexpr int scan_waves() {
-    constexpr bool one = SliceScan<MODE, SHORT, DENSE, false, false>::kByte1Only;
-    return (one && MODE != kModeBetween) ? 8 : (DENSE && MODE == kModeBetween && !one) ? 6 : 7;
-}
-
 template <int MODE, int SHORT, bool DENSE, bool HAS_IN, bool COUNT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(scan_waves<MODE, SHORT, DENSE>(), 8))) void k_scan_slices(
     const DevCol c, const ScanLit lit, const uint64_t* __restrict__ in_mask, uint64_t* __restrict__ out,

@@ -1,11 +1,13 @@
 // Scan of the slice layouts (PP-VBS, ByteSlice): one wave per 2048-row tile.
 //
-// Tile layout of a tile-interleaved slice (BS_1 of both layouts, every slice of
-// ByteSlice): lane L of the wave owns the 32 consecutive rows 32L .. 32L+31 of
-// the tile, so its 32 result bits are exactly dword L of the tile's 64 result
-// dwords.  Its bytes are eight dwords; dword i holds rows 8q + i (q = 0..3) in
-// byte q, dwords 0-3 at tile offset 16L and dwords 4-7 at 1024 + 16L, so each
-// 16-byte load instruction of the wave reads 1 KB contiguously.
+// Tile layout of a tile-interleaved slice (BS_1 of both layouts): lane L of the
+// wave owns the 32 consecutive rows 32L .. 32L+31 of the tile, so its 32 result
+// bits are exactly dword L of the tile's 64 result dwords.  Its bytes are eight
+// dwords; dword i holds rows 8q + i (q = 0..3) in byte q, dwords 0-3 at tile
+// offset 16L and dwords 4-7 at 1024 + 16L, so each 16-byte load instruction of
+// the wave reads 1 KB contiguously.  ByteSlice's later slices hold the same
+// eight dwords per lane contiguously at 32L: only lanes with pending rows read
+// them, and a lane's 32 bytes then sit in one cache line.
 //
 // Byte compares are four at a time inside a dword (SIMD within a register):
 // the high bit of every byte lane carries the outcome, and shifting dword i
@@ -200,9 +202,12 @@ struct TileData {
     uint32_t dir2;   // PP-VBS: BS_2 position of the tile's first byte 2 (all lanes)
 };
 
-// The lane's 32 bytes of a tile-interleaved slice, or zeros when `off` is out of range.
+// The lane's 32 bytes of a tile-interleaved slice (two 16-byte chunks `gap`
+// bytes apart: 1024 for BS_1, 16 for ByteSlice's later slices), or zeros when
+// `off` is out of range.
+template <uint32_t GAP = 1024>
 __device__ __forceinline__ void load_lane_bytes(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t (&x)[8]) {
-    const uint4 a = buffer_load16(r, off), b = buffer_load16(r, off + 1024);
+    const uint4 a = buffer_load16(r, off), b = buffer_load16(r, off + GAP);
     x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
     x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
 }
@@ -374,9 +379,10 @@ struct SliceScan {
         if (!wave_any(pend != 0)) return;
         if (COUNT) count_level(st, 2, pend, td.m2, lane);
         if constexpr (DENSE) {
-            // the pending lanes' 32 bytes of BS_2, in the same lane layout as BS_1
+            // the pending lanes' 32 bytes of BS_2 (contiguous per lane), held in the
+            // same registers as BS_1's
             const auto r2 = buffer_rsrc(c.bs[2] + t * kTileRows, kTileRows);
-            load_lane_bytes(r2, pend ? lane * 16 : kOutOfRange, s.d);
+            load_lane_bytes<16>(r2, pend ? lane * 32 : kOutOfRange, s.d);
             s.inflight = 1;
         } else {
             const uint32_t incl = wave_incl_sum((uint32_t)__builtin_popcount(td.m2));
@@ -496,7 +502,7 @@ struct SliceScan {
             if constexpr (DENSE) {
                 if (COUNT) count_level(st, j, pend, 0u, lane);
                 uint32_t x[8];
-                load_lane_bytes(buffer_rsrc(c.bs[j] + t * kTileRows, kTileRows), pend ? lane * 16 : kOutOfRange, x);
+                load_lane_bytes<16>(buffer_rsrc(c.bs[j] + t * kTileRows, kTileRows), pend ? lane * 32 : kOutOfRange, x);
                 lane_masks<MODE>(x, cl, ch, rlo, elo, rhi, ehi);
                 m = j < K ? ~0u : 0u;
             } else {
@@ -580,6 +586,18 @@ struct SliceScan {
         }
     }
 };
+
+// Waves per SIMD the variant is built for: 8 (64 VGPRs) where a tile's work
+// ends with its byte-1 pass; variants that keep a tile's later-byte reads in
+// flight (two tiles' gathered bytes or dense slice bytes besides two tiles'
+// loads), and BETWEEN with its two literals, are built for 7 (73 VGPRs);
+// ByteSlice BETWEEN with a multi-byte literal, whose tile state holds a lane's
+// 32 bytes of the second slice, for 6 (85 VGPRs).
+template <int MODE, int SHORT, bool DENSE>
+constexpr int scan_waves() {
+    constexpr bool one = SliceScan<MODE, SHORT, DENSE, false, false>::kByte1Only;
+    return (one && MODE != kModeBetween) ? 8 : (DENSE && MODE == kModeBetween && !one) ? 6 : 7;
+}
 
 template <int MODE, int SHORT, bool DENSE, bool HAS_IN, bool COUNT>
 __device__ __forceinline__ void scan_slices_range(const DevCol& c, const ScanLit& lit,

@@ -3,6 +3,8 @@ import ctypes
 import os
 import re
 
+import pytest
+
 from conftest import ROOT
 
 
@@ -32,3 +34,18 @@ def test_library_loads_without_gpu(built_lib):
     assert _lib.bst_version() >= 10000
     assert _lib.bst_device_count() >= 0
     assert _lib.bst_tune_get(99) == -1
+
+
+def test_tuning_keys_validated(built_lib):
+    """Tuning values are host state: the batch stream count is checked on set."""
+    from paper_2209_00220_amd import _lib
+
+    saved = _lib.bst_tune_get(_lib.TUNE_BATCH_STREAMS)
+    assert saved == 1
+    for bad in (0, 5, -1):
+        with pytest.raises(RuntimeError):
+            _lib.bst_tune_set(_lib.TUNE_BATCH_STREAMS, bad)
+    assert _lib.bst_tune_get(_lib.TUNE_BATCH_STREAMS) == saved
+    _lib.bst_tune_set(_lib.TUNE_BATCH_STREAMS, 3)
+    assert _lib.bst_tune_get(_lib.TUNE_BATCH_STREAMS) == 3
+    _lib.bst_tune_set(_lib.TUNE_BATCH_STREAMS, saved)

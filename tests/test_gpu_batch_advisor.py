@@ -44,13 +44,27 @@ def _mixed_items(seed=0, n_cols=6):
     return cols, xs, items
 
 
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_batch_equals_single(use_graph):
+RR = 0xFFFFFFFF   # tiles_per_grab: round-robin tiles, no counter
+
+
+@pytest.mark.parametrize("use_graph,streams,grab,grid", [(False, 1, 2, 0), (True, 1, RR, 0), (False, 4, RR, 0),
+                                                         (True, 2, 2, 0), (True, 4, RR, 3), (False, 1, RR, 3),
+                                                         (False, 2, 1, 5)])
+def test_batch_equals_single(use_graph, streams, grab, grid):
+    """Every item of a mixed batch (three layouts, every operator) equals the plain
+    definition, eager and replayed from a graph, with the groups on one stream or
+    spread over several (helper streams forked off and joined back), tiles taken
+    from a counter or assigned round robin; small grids give each wave many
+    tiles per item."""
     from paper_2209_00220_amd import _lib
     from paper_2209_00220_amd.batch import Batch
     from paper_2209_00220_amd.column import bv_to_numpy
 
-    cols, xs, items = _mixed_items(seed=1 if use_graph else 0)
+    assert _lib.BATCH_ROUND_ROBIN == RR
+    flush("batch equals single: graph=%s streams=%d grab=%d grid=%d" % (use_graph, streams, grab, grid))
+    cols, xs, items = _mixed_items(seed=(1 if use_graph else 0) + 2 * streams + (grab == RR))
+    saved = _lib.bst_tune_get(_lib.TUNE_BATCH_STREAMS)
+    _lib.bst_tune_set(_lib.TUNE_BATCH_STREAMS, streams)
     try:
         outs, specs = [], []
         for ci, lay, op, a, b in items:
@@ -71,7 +85,7 @@ def test_batch_equals_single(use_graph):
                 o.fill_(-1)
             first_out.fill_(0)
             first.launch(grid=0, tiles_per_grab=1, use_graph=use_graph)
-            batch.launch(grid=0, tiles_per_grab=2, use_graph=use_graph)
+            batch.launch(grid=grid, tiles_per_grab=grab, use_graph=use_graph)
             torch.cuda.synchronize()
             for k, ((ci, lay, op, a, b), o) in enumerate(zip(items, outs)):
                 x, w = xs[ci]
@@ -84,6 +98,7 @@ def test_batch_equals_single(use_graph):
         batch.close()
         first.close()
     finally:
+        _lib.bst_tune_set(_lib.TUNE_BATCH_STREAMS, saved)
         for c in cols:
             close_columns(c)
 
