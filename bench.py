@@ -561,7 +561,7 @@ def batch_main(args):
     import datagen
     from datagen import workloads
     from paper_2209_00220_amd import _lib as L
-    from paper_2209_00220_amd.batch import Batch, autotune, time_call
+    from paper_2209_00220_amd.batch import autotune_batch, time_call
     from paper_2209_00220_amd.column import DeviceColumn, Dictionary, HostColumn, bv_popcount
 
     torch.cuda.set_device(0)
@@ -596,12 +596,12 @@ def batch_main(args):
     tuned, _ = autotune_scan([(cols[c], op, lo, hi) for c, op, lo, hi, _ in preds])
     progress("scan launch tuned: grid %d, gather %d" % tuned)
     single_ms = _ms_events(singles)
-    b = Batch([(cols[c], op, lo, hi, None) for c, op, lo, hi, _ in preds], outs)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    best, table = autotune(b, grids=[cus * 2, cus * 3, cus * 4, cus * 8], grabs=(8, 16, 32, 64, L.BATCH_ROUND_ROBIN),
-                           streams=args.batch_streams, repeats=3)
-    one_stream = min(v for k, v in table.items() if k[2] == 1) if 1 in args.batch_streams else None
-    batch_ms = time_call(lambda: b.launch(best[0], best[1], True), repeats=5)
+    b, best, table = autotune_batch([(cols[c], op, lo, hi, None) for c, op, lo, hi, _ in preds], outs,
+                                    grids=[cus * 2, cus * 3, cus * 4, cus * 8],
+                                    grabs=(8, 16, 32, 64, L.BATCH_ROUND_ROBIN), streams=args.batch_streams, repeats=3)
+    one_stream = min(v for k, v in table.items() if k[3] == 1) if 1 in args.batch_streams else None
+    batch_ms = time_call(lambda: b.launch(best[1], best[2], True), repeats=5)
     torch.cuda.synchronize()
     # every result's popcount against the plain count from the value counts
     for (c, op, lo, hi, _), o in zip(preds, outs):
@@ -623,7 +623,8 @@ def batch_main(args):
                                "%d predicates (<, <=, =, BETWEEN; selectivity log-uniform 0.01-50%%)"
                                % (len(specs), len(preds)), "rows_scanned": rows},
         "batch_ms": round(batch_ms, 3), "single_launches_ms": round(single_ms, 3),
-        "speedup": round(single_ms / batch_ms, 3), "grid": best[0], "tiles_per_grab": _grab_name(best[1]), "streams": best[2],
+        "speedup": round(single_ms / batch_ms, 3), "solo_tiles": best[0], "grid": best[1],
+        "tiles_per_grab": _grab_name(best[2]), "streams": best[3],
         "one_stream_ms": None if one_stream is None else round(one_stream, 3),
         "alg_bytes": alg, "batch_hbm_frac": round(alg / (batch_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "single_gtuples": round(rows / (single_ms * 1e-3) / 1e9, 1),
@@ -1022,18 +1023,19 @@ def main():
     if args.batch:
         # the same step's scans as one persistent launch (replayed from a HIP graph)
         from paper_2209_00220_amd import _lib as L
-        from paper_2209_00220_amd.batch import Batch, autotune, time_call
+        from paper_2209_00220_amd.batch import autotune_batch, time_call
 
         progress("batched form: %d scans in one launch" % (len(layouts) * len(preds)))
         specs = [(cols[lay][1], op, lo, hi, None) for lay in layouts for op, lo, hi, _ in preds]
         outs = [cols[layouts[0]][1].new_bv() for _ in specs]
-        b = Batch(specs, outs)
         cus = torch.cuda.get_device_properties(0).multi_processor_count
-        best, table = autotune(b, grids=[cus * 2, cus * 3, cus * 4, cus * 8], grabs=(8, 16, 32, 64, L.BATCH_ROUND_ROBIN),
-                               streams=args.batch_streams, repeats=3)
-        batch_ms = time_call(lambda: b.launch(best[0], best[1], True), repeats=5)
+        b, best, table = autotune_batch(specs, outs, grids=[cus * 2, cus * 3, cus * 4, cus * 8],
+                                        grabs=(8, 16, 32, 64, L.BATCH_ROUND_ROBIN), streams=args.batch_streams,
+                                        repeats=3)
+        batch_ms = time_call(lambda: b.launch(best[1], best[2], True), repeats=5)
         single_ms = float(sum(sum(res[lay]["scan_ms"]) for lay in layouts))
-        out["batch"] = {"scans": len(specs), "grid": best[0], "tiles_per_grab": _grab_name(best[1]), "streams": best[2],
+        out["batch"] = {"scans": len(specs), "solo_tiles": best[0], "grid": best[1],
+                        "tiles_per_grab": _grab_name(best[2]), "streams": best[3],
                         "batch_ms": round(batch_ms, 3), "single_launches_ms": round(single_ms, 3),
                         "batch_gtuples": round(n * len(specs) / (batch_ms * 1e-3) / 1e9, 1)}
         progress("batch: %s" % json.dumps(out["batch"]))

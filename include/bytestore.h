@@ -336,7 +336,9 @@ int bst_batch_prepare(const bst_column* const* cols, const bst_pred* preds,
                       const uint64_t* const* in_masks, uint64_t* const* outs, int n_items,
                       void* workspace, bst_batch** out);
 /*
- * Run every scan of the batch: items are grouped by kernel variant (layout,
+ * Run every scan of the batch.  An item of at least BST_TUNE_BATCH_SOLO_TILES
+ * tiles (as set when the batch was prepared) runs as the single-column scan
+ * launch would run it.  The other items are grouped by kernel variant (layout,
  * operator or code width, one-byte literal, incoming mask), and each group is
  * one persistent launch of up to `grid` workgroups (0 = tuned default; never
  * more waves than the group has tiles) whose waves take at least
@@ -347,8 +349,8 @@ int bst_batch_prepare(const bst_column* const* cols, const bst_pred* preds,
  * tiles_per_grab = BST_BATCH_ROUND_ROBIN takes no counter: the group's tiles
  * (its items' tiles concatenated) go round robin over the launch's waves, so
  * each item is read as a single-column scan reads it.  With
- * BST_TUNE_BATCH_STREAMS = s > 1 the groups are spread over s streams (largest
- * group first, to the least loaded): helper streams of the library fork off
+ * BST_TUNE_BATCH_STREAMS = s > 1 the launches are spread over s streams (largest
+ * first, to the least loaded): helper streams of the library fork off
  * `stream` after the counter reset and join back into it before the call
  * returns, so later work on `stream` still sees every result.  The items must
  * be independent (no item's incoming mask is another item's output).  With
@@ -374,7 +376,12 @@ enum {
     BST_TUNE_BATCH_STREAMS = 5,/* streams a batch's groups are spread over (1..4,
                                   default 1): the caller's stream and library-owned
                                   helper streams forked from it and joined back   */
-    BST_TUNE_NKEYS = 6
+    BST_TUNE_BATCH_SOLO_TILES = 6, /* batch items of at least this many 2048-row tiles
+                                  (read when a batch is prepared; >= 1, default
+                                  16384) run as single-column scan launches with
+                                  their own launch shape instead of joining a
+                                  persistent group launch                          */
+    BST_TUNE_NKEYS = 7
 };
 int bst_tune_set(int key, int64_t value);
 int64_t bst_tune_get(int key);

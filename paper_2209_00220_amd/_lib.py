@@ -28,7 +28,8 @@ TILE_ROWS = 2048
 BATCH_ROUND_ROBIN = 0xFFFFFFFF   # tiles_per_grab: static round-robin tiles, no counter
 NBUF = 19
 BUF_BS1, BUF_BS2, BUF_M2, BUF_DIR2, BUF_PACKED, BUF_DICT, BUF_TRIE = 0, 1, 6, 11, 16, 17, 18
-TUNE_SCAN_GRID, TUNE_LOOKUP_GRID, TUNE_BATCH_GRID, TUNE_BATCH_GRAB, TUNE_GATHER_ROWS, TUNE_BATCH_STREAMS = 0, 1, 2, 3, 4, 5
+(TUNE_SCAN_GRID, TUNE_LOOKUP_GRID, TUNE_BATCH_GRID, TUNE_BATCH_GRAB, TUNE_GATHER_ROWS, TUNE_BATCH_STREAMS,
+ TUNE_BATCH_SOLO_TILES) = range(7)
 
 
 class BstError(RuntimeError):

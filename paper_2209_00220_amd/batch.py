@@ -93,6 +93,36 @@ def autotune(batch: Batch, grids=None, grabs=(1, 2, 4, 8, 16), streams=(1,), rep
     return best, results
 
 
+def autotune_batch(specs, outs, solos=(1 << 12, 1 << 14, 1 << 62), **kw):
+    """autotune() over the solo threshold as well: for every value of
+    TUNE_BATCH_SOLO_TILES (items of at least that many tiles run as single-column
+    scan launches; it is read when a batch is prepared) a Batch of `specs` is
+    prepared and its launch shape tuned.  Returns (the fastest Batch, open;
+    (solo, grid, tiles_per_grab, streams); {tuple: ms}).  The winning values
+    stay the library's defaults."""
+    saved = L.bst_tune_get(L.TUNE_BATCH_SOLO_TILES)
+    best, best_b, table = None, None, {}
+    try:
+        for solo in solos:
+            L.bst_tune_set(L.TUNE_BATCH_SOLO_TILES, solo)
+            b = Batch(specs, outs)
+            shape, res = autotune(b, **kw)
+            table.update({(solo,) + k: v for k, v in res.items()})
+            if best is None or res[shape] < table[best]:
+                if best_b is not None:
+                    best_b.close()
+                best, best_b = (solo,) + shape, b
+            else:
+                b.close()
+    finally:
+        L.bst_tune_set(L.TUNE_BATCH_SOLO_TILES, saved)
+    L.bst_tune_set(L.TUNE_BATCH_SOLO_TILES, best[0])
+    L.bst_tune_set(L.TUNE_BATCH_GRID, best[1])
+    L.bst_tune_set(L.TUNE_BATCH_GRAB, best[2])
+    L.bst_tune_set(L.TUNE_BATCH_STREAMS, best[3])
+    return best_b, best, table
+
+
 def autotune_scan(scans, grids=None, gathers=(1, 2, 4), repeats: int = 3):
     """Pick the single-column scan launch shape by timing: every (grid, gather)
     pair runs all `scans` -- (DeviceColumn, op, lo, hi) -- and the pair with the

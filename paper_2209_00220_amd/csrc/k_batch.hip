@@ -191,6 +191,7 @@ struct BatchGroup {
 struct bst_batch {
     std::vector<BatchItem> items;        // sorted by group
     std::vector<BatchGroup> groups;
+    std::vector<BatchItem> solo;         // items launched as single-column scans
     std::vector<std::pair<uint64_t*, std::pair<const uint64_t*, int>>> fills;   // (out, (in, all)) for ALL/NONE items
     std::vector<uint64_t> fill_rows;
     void* ws = nullptr;
@@ -250,6 +251,10 @@ int bst_batch_prepare(const bst_column* const* cols, const bst_pred* preds, cons
         it.out = outs[i];
         it.tile0 = tiles;
         it.kind = batch_kind(col, lit);
+        if ((int64_t)col->dev.ntiles >= g_tune[BST_TUNE_BATCH_SOLO_TILES]) {
+            b->solo.push_back(it);
+            continue;
+        }
         tiles += col->dev.ntiles;
         b->items.push_back(it);
     }
@@ -288,14 +293,16 @@ static int batch_enqueue(bst_batch* b, uint32_t grid, uint32_t grab, hipStream_t
         int rc = enqueue_fill(b->fills[i].first, b->fills[i].second.first, b->fill_rows[i], b->fills[i].second.second, st);
         if (rc) return rc;
     }
-    if (b->groups.empty()) return hip_check(hipGetLastError(), "batch launch");
-    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(128), 0, st, ws, (int)b->groups.size());
-    // Groups go to the least loaded of `ns` streams, largest first: a small group
-    // that cannot fill the chip, and the tail of each launch, overlap with other
-    // groups instead of idling the device.
-    const int ns = (int)std::min<uint64_t>(b->groups.size(),
-                                           std::max<int64_t>(1, std::min<int64_t>(g_tune[BST_TUNE_BATCH_STREAMS],
-                                                                                  kBatchStreamsMax)));
+    // units of work: the groups' persistent launches, then the solo items
+    const size_t n_units = b->groups.size() + b->solo.size();
+    if (n_units == 0) return hip_check(hipGetLastError(), "batch launch");
+    if (!b->groups.empty())
+        hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(128), 0, st, ws, (int)b->groups.size());
+    // Units go to the least loaded of `ns` streams, largest first: a group that
+    // cannot fill the chip, and the tail of each launch, overlap with other
+    // units instead of idling the device.
+    const int ns = (int)std::min<uint64_t>(n_units, std::max<int64_t>(1, std::min<int64_t>(g_tune[BST_TUNE_BATCH_STREAMS],
+                                                                                          kBatchStreamsMax)));
     ForkSet* fs = nullptr;
     hipStream_t lanes[kBatchStreamsMax] = {st};
     if (ns > 1) {
@@ -307,18 +314,30 @@ static int batch_enqueue(bst_batch* b, uint32_t grid, uint32_t grab, hipStream_t
         }
         if (rc) return rc;
     }
-    std::vector<uint32_t> order(b->groups.size());
-    for (size_t g = 0; g < order.size(); ++g) order[g] = (uint32_t)g;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t x, uint32_t y) { return b->groups[x].tiles > b->groups[y].tiles; });
+    auto unit_tiles = [&](size_t u) {
+        return u < b->groups.size() ? b->groups[u].tiles : b->solo[u - b->groups.size()].c.ntiles;
+    };
+    std::vector<uint32_t> order(n_units);
+    for (size_t u = 0; u < n_units; ++u) order[u] = (uint32_t)u;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return unit_tiles(x) > unit_tiles(y); });
     uint64_t load[kBatchStreamsMax] = {};
-    for (uint32_t g : order) {
-        const BatchGroup& gr = b->groups[g];
+    int rc = BST_OK;
+    for (uint32_t u : order) {
         int lane = 0;
         for (int i = 1; i < ns; ++i)
             if (load[i] < load[lane]) lane = i;
-        load[lane] += gr.tiles;
+        load[lane] += unit_tiles(u);
         const hipStream_t gs = lanes[lane];
+        if (u >= b->groups.size()) {
+            // a large item: the single-column kernel with its own launch shape
+            const BatchItem& it = b->solo[u - b->groups.size()];
+            const int r = it.c.layout == BST_BITPACKED ? launch_packed(it.c, it.pl, it.in_mask, it.out, nullptr, gs)
+                                                       : launch_slices(it.c, it.lit, it.in_mask, it.out, nullptr, gs);
+            if (!rc) rc = r;
+            continue;
+        }
+        const uint32_t g = u;
+        const BatchGroup& gr = b->groups[g];
         char* h = ws + g * kBatchHeaderBytes;
         // no more waves than the group has tiles
         const uint32_t grid_g = (uint32_t)std::max<uint64_t>(
@@ -337,10 +356,12 @@ static int batch_enqueue(bst_batch* b, uint32_t grid, uint32_t grab, hipStream_t
             take = std::max<uint64_t>(grab, (gr.tiles + 4 * waves - 1) / (4 * waves));
         if (take) take = std::min<uint64_t>(take, 1u << 20);
         hipLaunchKernelGGL(batch_kernel(gr.kind, gr.has_in), dim3(grid_g), dim3(kBlock), 0, gs,
-                           (const BatchHeader*)h, items + gr.first, (unsigned long long*)(h + 32),
-                           (uint32_t)take);
+                           (const BatchHeader*)h, items + gr.first, (unsigned long long*)(h + 32), (uint32_t)take);
     }
-    int rc = hip_check(hipGetLastError(), "batch launch");
+    {
+        const int r = hip_check(hipGetLastError(), "batch launch");
+        if (!rc) rc = r;
+    }
     for (int i = 1; i < ns; ++i) {   // join every helper back, also after an error
         int r2 = hip_check(hipEventRecord(fs->join[i - 1], lanes[i]), "batch join");
         if (!r2) r2 = hip_check(hipStreamWaitEvent(st, fs->join[i - 1], 0), "batch join");

@@ -214,7 +214,7 @@ DeviceProps& props() {
     return p;
 }
 
-int64_t g_tune[BST_TUNE_NKEYS] = {0, 0, 0, 16, 4, 1};
+int64_t g_tune[BST_TUNE_NKEYS] = {0, 0, 0, 16, 4, 1, 16384};
 
 PackedLit packed_literal(const HostColumn& h, const ScanLit& s) {
     PackedLit p{0, 0, (uint32_t)s.negate, 0};
@@ -610,6 +610,7 @@ int bst_tune_set(int key, int64_t value) {
     if (key < 0 || key >= BST_TUNE_NKEYS) return set_error(BST_EINVAL, "bad tuning key");
     if (key == BST_TUNE_BATCH_STREAMS && (value < 1 || value > 4))
         return set_error(BST_EINVAL, "batch streams must be 1..4");
+    if (key == BST_TUNE_BATCH_SOLO_TILES && value < 1) return set_error(BST_EINVAL, "solo tiles must be >= 1");
     g_tune[key] = value;
     return BST_OK;
 }

@@ -49,3 +49,13 @@ def test_tuning_keys_validated(built_lib):
     _lib.bst_tune_set(_lib.TUNE_BATCH_STREAMS, 3)
     assert _lib.bst_tune_get(_lib.TUNE_BATCH_STREAMS) == 3
     _lib.bst_tune_set(_lib.TUNE_BATCH_STREAMS, saved)
+
+
+def test_solo_threshold_validated(built_lib):
+    from paper_2209_00220_amd import _lib
+
+    saved = _lib.bst_tune_get(_lib.TUNE_BATCH_SOLO_TILES)
+    assert saved == 16384
+    with pytest.raises(RuntimeError):
+        _lib.bst_tune_set(_lib.TUNE_BATCH_SOLO_TILES, 0)
+    assert _lib.bst_tune_get(_lib.TUNE_BATCH_SOLO_TILES) == saved

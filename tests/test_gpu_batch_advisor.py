@@ -47,24 +47,27 @@ def _mixed_items(seed=0, n_cols=6):
 RR = 0xFFFFFFFF   # tiles_per_grab: round-robin tiles, no counter
 
 
-@pytest.mark.parametrize("use_graph,streams,grab,grid", [(False, 1, 2, 0), (True, 1, RR, 0), (False, 4, RR, 0),
-                                                         (True, 2, 2, 0), (True, 4, RR, 3), (False, 1, RR, 3),
-                                                         (False, 2, 1, 5)])
-def test_batch_equals_single(use_graph, streams, grab, grid):
+@pytest.mark.parametrize("use_graph,streams,grab,grid,solo", [
+    (False, 1, 2, 0, 16384), (True, 1, RR, 0, 16384), (False, 4, RR, 0, 16384), (True, 2, 2, 0, 16384),
+    (True, 4, RR, 3, 16384), (False, 1, RR, 3, 16384), (False, 2, 1, 5, 16384),
+    (False, 1, RR, 0, 64), (False, 3, 2, 0, 64), (True, 4, RR, 7, 64), (True, 2, 1, 0, 1)])
+def test_batch_equals_single(use_graph, streams, grab, grid, solo):
     """Every item of a mixed batch (three layouts, every operator) equals the plain
     definition, eager and replayed from a graph, with the groups on one stream or
     spread over several (helper streams forked off and joined back), tiles taken
     from a counter or assigned round robin; small grids give each wave many
-    tiles per item."""
+    tiles per item. Items of at least `solo` tiles run as single-column launches
+    (solo = 1: every item), side by side with the groups."""
     from paper_2209_00220_amd import _lib
     from paper_2209_00220_amd.batch import Batch
     from paper_2209_00220_amd.column import bv_to_numpy
 
     assert _lib.BATCH_ROUND_ROBIN == RR
-    flush("batch equals single: graph=%s streams=%d grab=%d grid=%d" % (use_graph, streams, grab, grid))
-    cols, xs, items = _mixed_items(seed=(1 if use_graph else 0) + 2 * streams + (grab == RR))
-    saved = _lib.bst_tune_get(_lib.TUNE_BATCH_STREAMS)
+    flush("batch equals single: graph=%s streams=%d grab=%d grid=%d solo=%d" % (use_graph, streams, grab, grid, solo))
+    cols, xs, items = _mixed_items(seed=(1 if use_graph else 0) + 2 * streams + (grab == RR) + 8 * (solo < 100))
+    saved = _lib.bst_tune_get(_lib.TUNE_BATCH_STREAMS), _lib.bst_tune_get(_lib.TUNE_BATCH_SOLO_TILES)
     _lib.bst_tune_set(_lib.TUNE_BATCH_STREAMS, streams)
+    _lib.bst_tune_set(_lib.TUNE_BATCH_SOLO_TILES, solo)
     try:
         outs, specs = [], []
         for ci, lay, op, a, b in items:
@@ -98,7 +101,8 @@ def test_batch_equals_single(use_graph, streams, grab, grid):
         batch.close()
         first.close()
     finally:
-        _lib.bst_tune_set(_lib.TUNE_BATCH_STREAMS, saved)
+        _lib.bst_tune_set(_lib.TUNE_BATCH_STREAMS, saved[0])
+        _lib.bst_tune_set(_lib.TUNE_BATCH_SOLO_TILES, saved[1])
         for c in cols:
             close_columns(c)
 
