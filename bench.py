@@ -139,15 +139,22 @@ def _is_step_kernel(name: str) -> bool:
     return not (s.startswith("k_scan_slices") and s.rstrip(">").endswith("true"))   # instrumented counters run
 
 
-def _step_launches(rows):
-    """The launches of the benchmark steps, in order: scans and lookups, without the
-    instrumented counter runs before them (Bit-Packed's counter runs use the plain
-    kernel, so the sequence starts at the first step's first slice-layout scan)."""
+def _step_launches(rows, n_steps: int, n_preds: int, layouts=LAYOUTS):
+    """The launches of the first `n_steps` benchmark steps, in order: each step is,
+    per layout, its scans and then one lookup.  The steps' lookups are the first
+    lookups of the run (the counter runs and the launch tuner before the steps
+    only scan), so the region ends at the step's last lookup and is counted back
+    from there."""
     seq = [r for r in rows if _is_step_kernel(r["Kernel_Name"])]
-    k = 0
-    while k < len(seq) and not _short(seq[k]["Kernel_Name"]).startswith("k_scan_slices"):
-        k += 1
-    return seq[k:]
+    lk = [k for k, r in enumerate(seq) if _short(r["Kernel_Name"]).startswith("k_lookup")]
+    per = len(layouts) * (n_preds + 1)
+    need = n_steps * len(layouts)
+    assert len(lk) >= need, "trace holds %d lookups, the steps need %d" % (len(lk), need)
+    end = lk[need - 1] + 1
+    region = seq[end - n_steps * per:end]
+    assert all(_short(region[k]["Kernel_Name"]).startswith("k_lookup") for k in range(n_preds, len(region), n_preds + 1)), \
+        "step launches out of order"
+    return region
 
 
 def _step_layout_order(n_preds: int, layouts):
@@ -163,8 +170,8 @@ def summarize_trace(trace_dir: str, steps: int, warmup: int, cmd: str, out_path:
     the default benchmark, plus the --stats table of the whole run."""
     import numpy as np
 
-    rows = _kernel_rows(os.path.join(trace_dir, "run_kernel_trace.csv"))
-    seq = _step_launches(rows)
+    rows = sorted(_kernel_rows(os.path.join(trace_dir, "run_kernel_trace.csv")), key=lambda r: int(r["Start_Timestamp"]))
+    seq = _step_launches(rows, warmup + steps, len(preds), layouts)
     order = _step_layout_order(len(preds), layouts)
     per = len(order)
     timed = seq[warmup * per:(warmup + steps) * per]
@@ -176,9 +183,10 @@ def summarize_trace(trace_dir: str, steps: int, warmup: int, cmd: str, out_path:
         dur.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
         names[key] = _short(r["Kernel_Name"])
     lines = ["rocprofv3 kernel trace of the default benchmark: 500M-row column, 20-bit Zipf(1.0) values,",
-             "%d predicates x %d layouts + a 5M-ID lookup per layout per step; %d warmup and %d timed steps," % (
+             "%d predicates x %d layouts + a 5M-ID lookup per layout per step; %d warmup and %d timed steps" % (
                  len(preds), len(layouts), warmup, steps),
-             "then the batched launch and the serving run (their kernels appear in the stats table only).",
+             "after the launch-shape tuner, then the batched launch and the serving run (the tuner's, the",
+             "batch's and the serving run's kernels appear in the stats table only).",
              "",
              "commands (repo root; TMPDIR=/tmp):",
              "  " + cmd,
@@ -207,6 +215,80 @@ def summarize_trace(trace_dir: str, steps: int, warmup: int, cmd: str, out_path:
         f.write("\n".join(lines) + "\n")
 
 
+BATCH_TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d gpurun_out/batchtrace -o run --output-format csv -- "
+                   "python3 bench.py --workload batch")
+
+
+def summarize_batch_trace(trace_dir: str, bench_json: str, out_path: str, n_preds: int, passes: int = 5):
+    """Device spans of the batched-scan workload from a rocprofv3 kernel trace of
+    `bench.py --workload batch`: its last `passes` passes of single launches (the
+    timed ones, right before the first batch launch) and its last `passes` batch
+    replays (each starts with the counter reset; the result checks follow)."""
+    import numpy as np
+
+    rows = sorted(_kernel_rows(os.path.join(trace_dir, "run_kernel_trace.csv")), key=lambda r: int(r["Start_Timestamp"]))
+    names = [_short(r["Kernel_Name"]) for r in rows]
+    t0 = [int(r["Start_Timestamp"]) for r in rows]
+    t1 = [int(r["End_Timestamp"]) for r in rows]
+    first_batch = next(k for k, n in enumerate(names) if n.startswith("k_reset_counters") or n.startswith("k_batch"))
+    single = [k for k in range(first_batch) if names[k].startswith("k_scan") or names[k].startswith("k_fill")]
+    single = single[-passes * n_preds:]
+    assert len(single) == passes * n_preds, "trace holds %d single launches before the batch" % len(single)
+    resets = [k for k, n in enumerate(names) if n.startswith("k_reset_counters")]
+    batch_kernels = ("k_reset_counters", "k_batch", "k_scan", "k_fill")
+    tail = next((k for k in range(resets[-1], len(rows)) if not names[k].startswith(batch_kernels)), len(rows))
+    marks = resets[-passes:] + [tail]
+
+    def span(ks):
+        return (max(t1[k] for k in ks) - min(t0[k] for k in ks)) / 1e6, sum(t1[k] - t0[k] for k in ks) / 1e6
+
+    s_sp = [span(single[i * n_preds:(i + 1) * n_preds]) for i in range(passes)]
+    b_ks = [list(range(marks[i], marks[i + 1])) for i in range(passes)]
+    b_sp = [span(ks) for ks in b_ks]
+    res = {}
+    with open(bench_json) as f:
+        for line in f:
+            if line.startswith("{"):
+                res = json.loads(line)
+    lines = ["Kernel trace of the batched-scan workload: %d predicates (<, <=, =, BETWEEN; selectivity" % n_preds,
+             "log-uniform 0.01-50 %) over 64 PP-VBS columns (n log-uniform in [1e6, 1e8], w in 8..32, Zipf s in",
+             "[0, 1.5]), 4.66 G rows scanned per pass.",
+             "",
+             "commands (repo root; TMPDIR=/tmp):",
+             "  " + BATCH_TRACE_CMD + " > gpurun_out/batchtrace.out",
+             "  python3 bench.py --summarize-batch-trace gpurun_out/batchtrace gpurun_out/batchtrace.out "
+             "--out profiles/batch_256preds_64cols_kernel_trace.txt",
+             "",
+             "%d single launches per pass (the tuned single-column launch shape), last %d passes; span = first" % (
+                 n_preds, passes),
+             "start to last end, busy = summed kernel time, ms:",
+             "  spans " + " ".join("%6.3f" % a for a, _ in s_sp) + "   median %.3f" % np.median([a for a, _ in s_sp]),
+             "  busy  " + " ".join("%6.3f" % b for _, b in s_sp) + "   median %.3f" % np.median([b for _, b in s_sp]),
+             "",
+             "one batch (graph replay with the autotuned shape: solo threshold %s tiles, grid %s, tiles per" % (
+                 res.get("solo_tiles"), res.get("grid")),
+             "grab %s, %s stream(s)), last %d replays, ms:" % (res.get("tiles_per_grab"), res.get("streams"), passes),
+             "  spans " + " ".join("%6.3f" % a for a, _ in b_sp) + "   median %.3f" % np.median([a for a, _ in b_sp]),
+             "  busy  " + " ".join("%6.3f" % b for _, b in b_sp) + "   median %.3f" % np.median([b for _, b in b_sp]),
+             "",
+             "kernels of the last replay (start relative to the replay's first kernel, duration, us):"]
+    base = t0[b_ks[-1][0]]
+    for k in b_ks[-1]:
+        lines.append("  %-52s start %8.1f  dur %8.1f" % (names[k][:52], (t0[k] - base) / 1e3, (t1[k] - t0[k]) / 1e3))
+    if res:
+        lines += ["", "bench.py's own HIP-event figures in the same run: batch %s ms, single launches %s ms (speedup %s)" % (
+            res.get("batch_ms"), res.get("single_launches_ms"), res.get("speedup")),
+            "value %s Gtuples/s, algorithmic bytes %s per pass (%.1f %% of 8 TB/s)" % (
+                res.get("value"), res.get("alg_bytes"), 100 * res.get("batch_hbm_frac", 0))]
+    lines += ["", "The profiler widens the gaps between the %d single launches (span %.3f ms); their summed" % (
+        n_preds, np.median([a for a, _ in s_sp])),
+        "kernel time (%.3f ms) bounds what a run without it can reach. The batch replay's span (%.3f ms)" % (
+            np.median([b for _, b in s_sp]), np.median([a for a, _ in b_sp])),
+        "is %.2fx less device time than that bound." % (np.median([b for _, b in s_sp]) / np.median([a for a, _ in b_sp]))]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def summarize_counters(fetch_dir: str, write_dir: str, cmds, out_path: str, preds, layouts=LAYOUTS):
     """HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
     WRITE_SIZE, in KiB per dispatch) of a one-step benchmark, each scaled by what
@@ -225,7 +307,7 @@ def summarize_counters(fetch_dir: str, write_dir: str, cmds, out_path: str, pred
     gib = float(1 << 30)
     f_scale = gib / (float(copy_f["Counter_Value"]) * 1024)   # the copy reads 1 GiB
     w_scale = gib / (float(copy_w["Counter_Value"]) * 1024)   # and writes 1 GiB
-    fs, ws = _step_launches(fr), _step_launches(wr)
+    fs, ws = _step_launches(fr, 1, len(preds), layouts), _step_launches(wr, 1, len(preds), layouts)
     order = _step_layout_order(len(preds), layouts)
     assert len(fs) == len(ws) == len(order), (len(fs), len(ws), len(order))
     lines = ["HBM traffic per launch of the benchmark step (500M-row column, 20-bit Zipf(1.0)), from",
@@ -811,8 +893,13 @@ def main():
     ap.add_argument("--summarize-trace", metavar="DIR", help="write a kernel-trace summary of DIR (CPU only)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write an HBM-traffic summary of two counter runs (CPU only)")
+    ap.add_argument("--summarize-batch-trace", nargs=2, metavar=("DIR", "BENCH_OUT"),
+                    help="write a kernel-trace summary of a --workload batch run (CPU only)")
     ap.add_argument("--out", help="summary file to write")
     args = ap.parse_args()
+    if args.summarize_batch_trace:
+        summarize_batch_trace(args.summarize_batch_trace[0], args.summarize_batch_trace[1], args.out, args.batch_preds)
+        return
     if args.summarize_trace or args.summarize_pmc:
         from datagen import workloads
 
