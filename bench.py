@@ -76,17 +76,37 @@ def read_traffic(key: str = "hbm_bytes_per_launch"):
     kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
-    kv = {}
+    kv, section, rows = {}, None, {}
     for line in open(TRAFFIC_FILE):
+        if line.endswith("launches (fetch and write MB per launch, scaled):\n"):
+            section = line.split()[0]
+            rows[section] = []
+            continue
+        if section and line.startswith("  ") and " fetch " in line:
+            f = line.split()
+            rows[section].append((f[0], float(f[f.index("fetch") + 1]) + float(f[f.index("write") + 1])))
+            continue
+        section = None
         if ":" in line:
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     if kv.get("kernel_hash") != kernel_hash():
         return None
+    # the PP-VBS table must be whole (every benchmark predicate and the lookup, once)
+    # and the stated figures must follow from its rows
+    pp = rows.get("ppvbs", [])
+    scans = [mb for op, mb in pp if op != "lookup"]
+    looks = [mb for op, mb in pp if op == "lookup"]
+    from datagen import workloads
+
+    if len(scans) != 3 * len(workloads.SELECTIVITIES) or len(looks) != 1:
+        return None
     try:
-        return float(kv[key])
+        want = float(kv[key])
     except (KeyError, ValueError):
         return None
+    got = (sum(scans) / len(scans) if key == "hbm_bytes_per_launch" else looks[0]) * 1e6
+    return want if abs(got - want) <= 1e5 else None
 
 
 LINE_BYTES = 128   # a random access fills one L2 line of 128 bytes on this chip
