@@ -369,6 +369,50 @@ def summarize_counters(fetch_dir: str, write_dir: str, cmds, out_path: str, pred
         f.write("\n".join(lines) + "\n")
 
 
+WAIT_CMD = ("rocprofv3 --pmc SQ_WAIT_ANY SQ_WAVE_CYCLES -d gpurun_out/pmc_wait -o run --output-format csv -- "
+            "python3 bench.py --steps 1 --warmup 0 --no-batch --serve-queries 0 --no-cpu-baseline")
+
+
+def summarize_wait(wait_dir: str, out_path: str, preds, layouts=LAYOUTS):
+    """The share of wave cycles spent waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES) of
+    every launch of a one-step benchmark, from one rocprofv3 --pmc run."""
+    import numpy as np
+
+    rows = _kernel_rows(os.path.join(wait_dir, "run_counter_collection.csv"))
+    by = {}
+    for r in rows:
+        d = by.setdefault(int(r["Dispatch_Id"]), {"Kernel_Name": r["Kernel_Name"], "Dispatch_Id": r["Dispatch_Id"]})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+    seq = [by[k] for k in sorted(by)]
+    steps = _step_launches(seq, 1, len(preds), layouts)
+    order = _step_layout_order(len(preds), layouts)
+    lines = ["Share of wave cycles spent waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES) per launch of the",
+             "benchmark step (500M-row column, 20-bit Zipf(1.0)), from one rocprofv3 counter run; kernel_hash",
+             "names the scan kernel sources the counters were taken on.",
+             "",
+             "commands (repo root; TMPDIR=/tmp):",
+             "  " + WAIT_CMD,
+             "  python3 bench.py --summarize-wait gpurun_out/pmc_wait --out profiles/scan_lookup_500M_wait.txt",
+             ""]
+    cur = None
+    for (lay, i), r in zip(order, steps):
+        if lay != cur:
+            if cur:
+                lines.append("")
+            lines.append("%s launches:" % lay)
+            cur = lay
+        share = r.get("SQ_WAIT_ANY", 0.0) / max(r.get("SQ_WAVE_CYCLES", 0.0), 1.0)
+        if i == "lookup":
+            lines.append("  %-8s %-16s %-45s wait %.3f" % ("lookup", "5M ids", _short(r["Kernel_Name"]), share))
+        else:
+            op, lo, hi, _ = preds[i]
+            lit = "%d..%d" % (lo, hi) if hi is not None else "%d" % lo
+            lines.append("  %-8s %-16s %-45s wait %.3f" % (op, lit, _short(r["Kernel_Name"]), share))
+    lines += ["", "kernel_hash: %s" % kernel_hash()]
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -913,6 +957,7 @@ def main():
     ap.add_argument("--summarize-trace", metavar="DIR", help="write a kernel-trace summary of DIR (CPU only)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write an HBM-traffic summary of two counter runs (CPU only)")
+    ap.add_argument("--summarize-wait", metavar="DIR", help="write a wait-share summary of a counter run (CPU only)")
     ap.add_argument("--summarize-batch-trace", nargs=2, metavar=("DIR", "BENCH_OUT"),
                     help="write a kernel-trace summary of a --workload batch run (CPU only)")
     ap.add_argument("--out", help="summary file to write")
@@ -920,11 +965,13 @@ def main():
     if args.summarize_batch_trace:
         summarize_batch_trace(args.summarize_batch_trace[0], args.summarize_batch_trace[1], args.out, args.batch_preds)
         return
-    if args.summarize_trace or args.summarize_pmc:
+    if args.summarize_trace or args.summarize_pmc or args.summarize_wait:
         from datagen import workloads
 
         preds = workloads.config2_predicates(args.rows)
-        if args.summarize_trace:
+        if args.summarize_wait:
+            summarize_wait(args.summarize_wait, args.out, preds)
+        elif args.summarize_trace:
             summarize_trace(args.summarize_trace, args.steps, args.warmup, TRACE_CMD, args.out, preds)
         else:
             summarize_counters(args.summarize_pmc[0], args.summarize_pmc[1], PMC_CMDS, args.out, preds)

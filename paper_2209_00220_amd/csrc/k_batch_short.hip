@@ -5,10 +5,11 @@
 namespace bst {
 namespace dev {
 
-BatchKernel batch_short_kernel(int mi, bool dense, bool has_in) {
-#define BST_K(MODE, SH)                                                                                    \
-    return dense ? (has_in ? k_batch_slices<MODE, SH, true, true> : k_batch_slices<MODE, SH, true, false>) \
-                 : (has_in ? k_batch_slices<MODE, SH, false, true> : k_batch_slices<MODE, SH, false, false>)
+BatchKernel batch_short_kernel(int mi, bool dense, bool has_in, bool rr) {
+#define BST_KR(MODE, SH, RR)                                                                           \
+    (dense ? (has_in ? k_batch_slices<MODE, SH, true, true, RR> : k_batch_slices<MODE, SH, true, false, RR>) \
+           : (has_in ? k_batch_slices<MODE, SH, false, true, RR> : k_batch_slices<MODE, SH, false, false, RR>))
+#define BST_K(MODE, SH) return rr ? BST_KR(MODE, SH, true) : BST_KR(MODE, SH, false)
     switch (mi) {
         case 0: BST_K(kModeLT, 1);
         case 1: BST_K(kModeGT, 1);
@@ -16,6 +17,7 @@ BatchKernel batch_short_kernel(int mi, bool dense, bool has_in) {
         default: BST_K(kModeBetween, 3);
     }
 #undef BST_K
+#undef BST_KR
 }
 
 }  // namespace dev
