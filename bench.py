@@ -1183,9 +1183,10 @@ def main():
         specs = [(cols[lay][1], op, lo, hi, None) for lay in layouts for op, lo, hi, _ in preds]
         outs = [cols[layouts[0]][1].new_bv() for _ in specs]
         cus = torch.cuda.get_device_properties(0).multi_processor_count
+        # one stream: every one of these 500M-row scans fills the device alone (and
+        # runs solo), so spreading them over streams has never paid here
         b, best, table = autotune_batch(specs, outs, grids=[cus * 2, cus * 3, cus * 4, cus * 8],
-                                        grabs=(8, 16, 32, 64, L.BATCH_ROUND_ROBIN), streams=args.batch_streams,
-                                        repeats=3)
+                                        grabs=(8, 16, 32, 64, L.BATCH_ROUND_ROBIN), streams=(1,), repeats=3)
         batch_ms = time_call(lambda: b.launch(best[1], best[2], True), repeats=5)
         single_ms = float(sum(sum(res[lay]["scan_ms"]) for lay in layouts))
         out["batch"] = {"scans": len(specs), "solo_tiles": best[0], "grid": best[1],

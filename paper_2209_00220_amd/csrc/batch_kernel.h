@@ -27,28 +27,53 @@ __device__ __forceinline__ uint64_t batch_next_take(unsigned long long* counter,
     return fixed + s;
 }
 
-// The takes of a wave, item by item (a take may straddle items): segments
-// (item, first tile, end tile) of consecutive tiles, produced one at a time.
-struct BatchTakes {
+// The segments (item, first tile, end tile, stride) a wave scans, one at a
+// time, so that a kernel inlines its tile scan once for both assignments:
+//  * takes (grab > 0): consecutive tiles of the group's concatenated tile list,
+//    item by item (a take may straddle items), stride 1;
+//  * round robin (grab == 0): the group's tile g goes to wave g mod W of the W
+//    waves in the launch, so each item is scanned as a single-column launch
+//    scans it (a wave takes every W-th tile, neighbouring waves neighbouring
+//    tiles), the waves get equal tile counts within one, and no counter is
+//    touched.
+struct BatchSegments {
     const BatchItem* __restrict__ items;
     unsigned long long* __restrict__ counter;
-    uint64_t total, start, stop;
+    uint64_t total, start, stop, waves, wave;
     uint32_t n_items, grab, lane, cur;
 
-    __device__ __forceinline__ BatchTakes(const BatchHeader* __restrict__ hdr, const BatchItem* __restrict__ it,
-                                          unsigned long long* __restrict__ ctr, uint32_t g, uint32_t ln)
-        : items(it), counter(ctr), total(hdr->total_tiles), start(batch_first_take(g)), stop(0),
+    __device__ __forceinline__ BatchSegments(const BatchHeader* __restrict__ hdr, const BatchItem* __restrict__ it,
+                                             unsigned long long* __restrict__ ctr, uint32_t g, uint32_t ln)
+        : items(it), counter(ctr), total(hdr->total_tiles), start(0), stop(0),
+          waves((uint64_t)gridDim.x * kWavesPerBlock), wave(uniform(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6))),
           n_items(hdr->n_items), grab(g), lane(ln), cur(0) {
-        stop = std::min<uint64_t>(total, start + grab);
-        cur = start < total ? batch_find(items, n_items, start) : n_items;
+        if (grab) {
+            start = batch_first_take(grab);
+            stop = std::min<uint64_t>(total, start + grab);
+            cur = start < total ? batch_find(items, n_items, start) : n_items;
+        }
     }
 
-    __device__ __forceinline__ bool next(uint32_t& item, uint64_t& b0, uint64_t& b1) {
+    __device__ __forceinline__ bool next(uint32_t& item, uint64_t& b0, uint64_t& b1, uint64_t& stride) {
+        if (!grab) {
+            for (; cur < n_items; ++cur) {
+                const uint64_t first = (wave + waves - items[cur].tile0 % waves) % waves;
+                if (first < items[cur].c.ntiles) {
+                    item = cur++;
+                    b0 = first;
+                    b1 = items[item].c.ntiles;
+                    stride = waves;
+                    return true;
+                }
+            }
+            return false;
+        }
         while (start < total) {
             if (cur < n_items && items[cur].tile0 < stop) {
                 const BatchItem& it = items[cur];
                 b0 = std::max<uint64_t>(start, it.tile0) - it.tile0;
                 b1 = std::min<uint64_t>(stop, it.tile0 + it.c.ntiles) - it.tile0;
+                stride = 1;
                 item = cur++;
                 return true;
             }
@@ -61,25 +86,6 @@ struct BatchTakes {
     }
 };
 
-// Round robin: the group's tile g (its items' tiles concatenated) goes to wave
-// g mod W of the W waves in the launch.  Each item is then scanned as a
-// single-column launch scans it (a wave takes every W-th tile, neighbouring
-// waves neighbouring tiles), the waves get equal tile counts within one, and
-// no counter is touched.  scan(item, first, end, stride) per item the wave has
-// tiles of.  Its own kernel variant: it holds less loop state than takes.
-template <typename F>
-__device__ __forceinline__ void batch_round_robin(const BatchHeader* __restrict__ hdr,
-                                                  const BatchItem* __restrict__ items, F&& scan) {
-    const uint64_t W = (uint64_t)gridDim.x * kWavesPerBlock;
-    const uint64_t w = uniform(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
-    const uint32_t n_items = hdr->n_items;
-    for (uint32_t i = 0; i < n_items; ++i) {
-        const BatchItem& it = items[i];
-        const uint64_t first = (w + W - it.tile0 % W) % W;
-        if (first < it.c.ntiles) scan(it, first, it.c.ntiles, W);
-    }
-}
-
 // Waves per SIMD a batch variant is built for: the single-column variant's
 // where a tile ends with its byte-1 pass; kMinWaves where later levels are read,
 // since the item loop around the tile state needs the registers.
@@ -89,9 +95,9 @@ constexpr int batch_waves() {
                                                                                     : kMinWaves;
 }
 
-// Waves scan their takes (RR false) or their round-robin tiles (RR true); the
-// per-tile work is the single-column scan's, inlined.
-template <int MODE, int SHORT, bool DENSE, bool HAS_IN, bool RR>
+// Waves scan their segments (BatchSegments); the per-tile work is the
+// single-column scan's, inlined.
+template <int MODE, int SHORT, bool DENSE, bool HAS_IN>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batch_waves<MODE, SHORT, DENSE>(), 8))) void k_batch_slices(
     const BatchHeader* __restrict__ hdr, const BatchItem* __restrict__ items, unsigned long long* __restrict__ counter,
     uint32_t grab) {
@@ -99,20 +105,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batch_wa
     uint8_t* lds = stage[threadIdx.x >> 6];
     const uint32_t lane = threadIdx.x & 63;
     Stats st;
-    if constexpr (RR) {
-        batch_round_robin(hdr, items, [&](const BatchItem& it, uint64_t b0, uint64_t b1, uint64_t stride) {
-            scan_slices_range<MODE, SHORT, DENSE, HAS_IN, false>(it.c, it.lit, it.in_mask, it.out, b0, b1, stride,
-                                                                  lane, lds, st);
-        });
-    } else {
-        BatchTakes takes(hdr, items, counter, grab, lane);
-        uint32_t i;
-        uint64_t b0, b1;
-        while (takes.next(i, b0, b1)) {
-            const BatchItem& it = items[uniform(i)];
-            scan_slices_range<MODE, SHORT, DENSE, HAS_IN, false>(it.c, it.lit, it.in_mask, it.out, b0, b1, 1, lane,
-                                                                  lds, st);
-        }
+    BatchSegments seg(hdr, items, counter, grab, lane);
+    uint32_t i;
+    uint64_t b0, b1, stride;
+    while (seg.next(i, b0, b1, stride)) {
+        const BatchItem& it = items[uniform(i)];
+        scan_slices_range<MODE, SHORT, DENSE, HAS_IN, false>(it.c, it.lit, it.in_mask, it.out, b0, b1, stride, lane,
+                                                              lds, st);
     }
 }
 

@@ -342,12 +342,11 @@ __device__ __forceinline__ uint32_t batch_find(const BatchItem* __restrict__ ite
 }
 
 using BatchKernel = void (*)(const BatchHeader*, const BatchItem*, unsigned long long*, uint32_t);
-// Persistent Bit-Packed batch kernel for code width w (nullptr outside 1..32);
-// rr: the round-robin variant, else the one that takes tiles from a counter.
-BatchKernel batch_packed_kernel(uint32_t w, bool has_in, bool rr);
+// Persistent Bit-Packed batch kernel for code width w (nullptr outside 1..32).
+BatchKernel batch_packed_kernel(uint32_t w, bool has_in);
 // Persistent slice-layout batch kernel for one-byte literals; mi: 0 '<', 1 '>',
-// 2 '=', 3 BETWEEN; rr as above.
-BatchKernel batch_short_kernel(int mi, bool dense, bool has_in, bool rr);
+// 2 '=', 3 BETWEEN.
+BatchKernel batch_short_kernel(int mi, bool dense, bool has_in);
 
 
 // ------------------------------------------------------------ host helpers

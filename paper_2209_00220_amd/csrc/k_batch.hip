@@ -26,17 +26,16 @@ __global__ void k_reset_counters(char* __restrict__ ws, int n_groups) {
 
 
 // Kernel of a group: kind (see batch_kind) and whether its items have an incoming mask.
-static BatchKernel batch_kernel(uint32_t kind, bool has_in, bool rr) {
+static BatchKernel batch_kernel(uint32_t kind, bool has_in) {
     if (kind < 16) {
         const bool dense = kind & 1;
         const int mi = (kind >> 1) & 3;
-        if (kind & 8) return batch_short_kernel(mi, dense, has_in, rr);
+        if (kind & 8) return batch_short_kernel(mi, dense, has_in);
         // a '<', '>' or '=' literal that is not one byte is longer (SHORT = 0); a
         // BETWEEN may have one short bound, decided per item (SHORT = -1)
-#define BST_KR(MODE, SH, RR)                                                                           \
-    (dense ? (has_in ? k_batch_slices<MODE, SH, true, true, RR> : k_batch_slices<MODE, SH, true, false, RR>) \
-           : (has_in ? k_batch_slices<MODE, SH, false, true, RR> : k_batch_slices<MODE, SH, false, false, RR>))
-#define BST_K(MODE, SH) return rr ? BST_KR(MODE, SH, true) : BST_KR(MODE, SH, false)
+#define BST_K(MODE, SH)                                                                                    \
+    return dense ? (has_in ? k_batch_slices<MODE, SH, true, true> : k_batch_slices<MODE, SH, true, false>) \
+                 : (has_in ? k_batch_slices<MODE, SH, false, true> : k_batch_slices<MODE, SH, false, false>)
         switch (mi) {
             case 0: BST_K(kModeLT, 0);
             case 1: BST_K(kModeGT, 0);
@@ -44,9 +43,8 @@ static BatchKernel batch_kernel(uint32_t kind, bool has_in, bool rr) {
             default: BST_K(kModeBetween, -1);
         }
 #undef BST_K
-#undef BST_KR
     }
-    return batch_packed_kernel(kind - 16, has_in, rr);
+    return batch_packed_kernel(kind - 16, has_in);
 }
 
 }  // namespace dev
@@ -276,7 +274,7 @@ int bst_batch_prepare(const bst_column* const* cols, const bst_pred* preds, cons
             sorted.push_back(it);
             ++g.count;
         }
-        if (!batch_kernel(g.kind, g.has_in, false)) {
+        if (!batch_kernel(g.kind, g.has_in)) {
             delete b;
             return set_error(BST_EINVAL, "no batch kernel for this column");
         }
@@ -348,7 +346,7 @@ static int batch_enqueue(bst_batch* b, uint32_t grid, uint32_t grab, hipStream_t
         // A small group spreads over all its waves, one take each.  A large one
         // takes at least `grab` tiles at a time and no more than about four
         // takes per wave: every take is an atomic on the group's one counter.
-        // Round robin takes no counter: its own kernel variant, passed 0.
+        // Round robin passes 0.
         uint64_t take;
         if (grab == BST_BATCH_ROUND_ROBIN)
             take = 0;
@@ -357,7 +355,7 @@ static int batch_enqueue(bst_batch* b, uint32_t grid, uint32_t grab, hipStream_t
         else
             take = std::max<uint64_t>(grab, (gr.tiles + 4 * waves - 1) / (4 * waves));
         if (take) take = std::min<uint64_t>(take, 1u << 20);
-        hipLaunchKernelGGL(batch_kernel(gr.kind, gr.has_in, take == 0), dim3(grid_g), dim3(kBlock), 0, gs,
+        hipLaunchKernelGGL(batch_kernel(gr.kind, gr.has_in), dim3(grid_g), dim3(kBlock), 0, gs,
                            (const BatchHeader*)h, items + gr.first, (unsigned long long*)(h + 32), (uint32_t)take);
     }
     {
@@ -393,8 +391,8 @@ int bst_batch_launch(bst_batch* b, uint32_t grid, uint32_t tiles_per_grab, int u
     if (!use_graph) return batch_enqueue(b, grid, tiles_per_grab, st);
     if (!b->exec || b->graph_grid != grid || b->graph_grab != tiles_per_grab ||
         b->graph_streams != g_tune[BST_TUNE_BATCH_STREAMS]) {
-        if (b->exec) hipGraphExecDestroy(b->exec);
-        if (b->graph) hipGraphDestroy(b->graph);
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
         b->exec = nullptr;
         b->graph = nullptr;
         hipStream_t cap;
@@ -407,7 +405,7 @@ int bst_batch_launch(bst_batch* b, uint32_t grid, uint32_t tiles_per_grab, int u
             if (!rc) rc = rc2;
         }
         if (!rc) rc = hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
-        hipStreamDestroy(cap);
+        (void)hipStreamDestroy(cap);
         if (rc) return rc;
         b->graph_grid = grid;
         b->graph_grab = tiles_per_grab;
@@ -418,8 +416,8 @@ int bst_batch_launch(bst_batch* b, uint32_t grid, uint32_t tiles_per_grab, int u
 
 void bst_batch_free(bst_batch* b) {
     if (!b) return;
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     delete b;
 }
 

@@ -5,11 +5,10 @@
 namespace bst {
 namespace dev {
 
-BatchKernel batch_short_kernel(int mi, bool dense, bool has_in, bool rr) {
-#define BST_KR(MODE, SH, RR)                                                                           \
-    (dense ? (has_in ? k_batch_slices<MODE, SH, true, true, RR> : k_batch_slices<MODE, SH, true, false, RR>) \
-           : (has_in ? k_batch_slices<MODE, SH, false, true, RR> : k_batch_slices<MODE, SH, false, false, RR>))
-#define BST_K(MODE, SH) return rr ? BST_KR(MODE, SH, true) : BST_KR(MODE, SH, false)
+BatchKernel batch_short_kernel(int mi, bool dense, bool has_in) {
+#define BST_K(MODE, SH)                                                                                    \
+    return dense ? (has_in ? k_batch_slices<MODE, SH, true, true> : k_batch_slices<MODE, SH, true, false>) \
+                 : (has_in ? k_batch_slices<MODE, SH, false, true> : k_batch_slices<MODE, SH, false, false>)
     switch (mi) {
         case 0: BST_K(kModeLT, 1);
         case 1: BST_K(kModeGT, 1);
@@ -17,7 +16,6 @@ BatchKernel batch_short_kernel(int mi, bool dense, bool has_in, bool rr) {
         default: BST_K(kModeBetween, 3);
     }
 #undef BST_K
-#undef BST_KR
 }
 
 }  // namespace dev

@@ -330,7 +330,11 @@ int bst_upload(const bst_host_column* hc, void* const dev_bufs[BST_NBUF], void* 
     c.packed = (const uint32_t*)dev_bufs[BST_BUF_PACKED];
     c.dict = (const uint32_t*)dev_bufs[BST_BUF_DICT];
     c.trie = (const uint32_t*)dev_bufs[BST_BUF_TRIE];
-    hipGetDevice(&col->device);
+    int rc = hip_check(hipGetDevice(&col->device), "upload device");
+    if (rc) {
+        delete col;
+        return rc;
+    }
     *out = col;
     return BST_OK;
 }
@@ -569,7 +573,7 @@ int bst_advise(const bst_column* const* cands, int n_cand, int op, const uint32_
     if (rc) return rc;
     rc = hip_check(hipEventCreate(&e1), "event");
     if (rc) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return rc;
     }
     std::vector<int> layouts(n_cand);
@@ -585,9 +589,9 @@ int bst_advise(const bst_column* const* cands, int n_cand, int op, const uint32_
             if (rc) break;
             rc = run_scan(col, lit, nullptr, scratch_bv, nullptr, st);   // warm-up
             for (int r = 0; r < repeats && !rc; ++r) {
-                hipEventRecord(e0, st);
-                rc = run_scan(col, lit, nullptr, scratch_bv, nullptr, st);
-                hipEventRecord(e1, st);
+                rc = hip_check(hipEventRecord(e0, st), "event record");
+                if (!rc) rc = run_scan(col, lit, nullptr, scratch_bv, nullptr, st);
+                if (!rc) rc = hip_check(hipEventRecord(e1, st), "event record");
                 if (!rc) rc = hip_check(hipEventSynchronize(e1), "event sync");
                 float ms = 0;
                 if (!rc) rc = hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
@@ -600,8 +604,8 @@ int bst_advise(const bst_column* const* cands, int n_cand, int op, const uint32_
         }
         if (!rc) rc = bst_auc(sels, t.data(), n_lit, &auc_out[ci]);
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc) return rc;
     return bst_choose(layouts.data(), auc_out, n_cand, chosen);
 }
