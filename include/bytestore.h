@@ -184,10 +184,11 @@ int bst_host_paper_view(const bst_host_column* c, int part, int j, void* out, ui
 /* ---- residency --------------------------------------------------------- */
 /*
  * Copy a host column into caller-allocated device buffers (dev_bufs[slot] of
- * at least info.bytes[slot] bytes; unused slots may be NULL) with
- * hipMemcpyAsync on `stream`, and return a handle that pairs the device
+ * at least info.bytes[slot] bytes, 16-byte aligned; unused slots may be NULL)
+ * with hipMemcpyAsync on `stream`, and return a handle that pairs the device
  * pointers with the host metadata used to rewrite literals.  The host column
  * must outlive the handle; the device buffers stay owned by the caller.
+ * Errors: BST_EINVAL for a missing or misaligned buffer.
  */
 int bst_upload(const bst_host_column* c, void* const dev_bufs[BST_NBUF], void* stream,
                bst_column** out);

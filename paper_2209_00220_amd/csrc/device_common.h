@@ -100,15 +100,38 @@ struct Stats {
     uint64_t alg = 0, rowbytes = 0, deep_groups = 0, full = 0;
 };
 
-// Position in BS_j of the first j-th byte of 64-row group g (PP-VBS): the
-// directory entry at or before the group plus the mask popcounts in between.
-__device__ __forceinline__ uint64_t vbs_group_base(const DevCol& c, uint32_t j, uint64_t g) {
-    const uint64_t row = g << 6;
-    const uint64_t q = row >> c.dir_shift;
-    uint64_t base = c.dir[j][q];
-    const uint64_t* m = c.m[j];
-    for (uint64_t gg = (q << c.dir_shift) >> 6; gg < g; ++gg) base += __builtin_popcountll(m[gg]);
-    return base;
+// M_j word of 64-row group g (PP-VBS), and in `before` the j-th bytes of the
+// groups before g in its directory block (the position of g's first j-th byte
+// is the block's directory entry plus `before`).  A block of up to 8 words is
+// one aligned 64-byte run, read with independent 16-byte loads, so the mask
+// and the walk cost one round trip together, in the line the mask needs anyway.
+__device__ __forceinline__ uint64_t vbs_word(const DevCol& c, uint32_t j, uint64_t g, uint64_t& before) {
+    const uint32_t lw = c.dir_shift - 6;   // log2 of the M_j words per directory block
+    const uint64_t b0 = (g >> lw) << lw;
+    const uint32_t k = (uint32_t)(g - b0);
+    const uint64_t* m = c.m[j] + b0;
+    before = 0;
+    if (lw == 0 || lw > 3) {
+        for (uint32_t i = 0; i < k; ++i) before += __builtin_popcountll(m[i]);
+        return m[k];
+    }
+    const uint32_t pairs = 1u << (lw - 1);   // 16-byte pairs in the block: 1, 2 or 4
+    const ulonglong2* p = reinterpret_cast<const ulonglong2*>(m);
+    ulonglong2 v[4];
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) {
+        if (i < pairs) v[i] = p[i];
+        else v[i] = make_ulonglong2(0, 0);
+    }
+    uint64_t w = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) {
+        if (2 * i < k) before += __builtin_popcountll(v[i].x);
+        if (2 * i + 1 < k) before += __builtin_popcountll(v[i].y);
+        if (2 * i == k) w = v[i].x;
+        if (2 * i + 1 == k) w = v[i].y;
+    }
+    return w;
 }
 
 // ------------------------------------------------------------ raw buffer access
@@ -284,10 +307,12 @@ __device__ __forceinline__ uint32_t lookup_row(const DevCol& c, uint64_t r) {
         uint32_t len = 1;
         const uint64_t g = r >> 6;
         const uint64_t below = (1ull << (r & 63)) - 1;
+        const uint32_t lw = c.dir_shift - 6;
         for (uint32_t j = 2; j <= c.K; ++j) {
-            const uint64_t w = c.m[j][g];
+            uint64_t before;
+            const uint64_t w = vbs_word(c, j, g, before);
             if (!((w >> (r & 63)) & 1)) break;
-            const uint64_t off = vbs_group_base(c, j, g) + __builtin_popcountll(w & below);
+            const uint64_t off = c.dir[j][g >> lw] + before + __builtin_popcountll(w & below);
             code = (code << 8) | c.bs[j][off];
             len = j;
         }

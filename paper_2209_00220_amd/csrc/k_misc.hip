@@ -300,6 +300,8 @@ int bst_upload(const bst_host_column* hc, void* const dev_bufs[BST_NBUF], void* 
     for (int s = 0; s < BST_NBUF; ++s) {
         if (h.buf[s].empty()) continue;
         if (!dev_bufs[s]) return set_error(BST_EINVAL, "missing device buffer for slot " + std::to_string(s));
+        if (reinterpret_cast<uintptr_t>(dev_bufs[s]) % 16)
+            return set_error(BST_EINVAL, "device buffer for slot " + std::to_string(s) + " is not 16-byte aligned");
         int rc = hip_check(hipMemcpyAsync(dev_bufs[s], h.buf[s].data(), h.buf[s].size(), hipMemcpyHostToDevice, st),
                            "upload");
         if (rc) return rc;

@@ -59,3 +59,23 @@ def test_solo_threshold_validated(built_lib):
     with pytest.raises(RuntimeError):
         _lib.bst_tune_set(_lib.TUNE_BATCH_SOLO_TILES, 0)
     assert _lib.bst_tune_get(_lib.TUNE_BATCH_SOLO_TILES) == saved
+
+
+def test_upload_rejects_misaligned_buffers(built_lib):
+    """bst_upload checks every used device buffer for 16-byte alignment before it
+    copies anything (so this runs without a GPU: no HIP call is reached)."""
+    import numpy as np
+
+    from paper_2209_00220_amd import _lib
+    from paper_2209_00220_amd.column import HostColumn
+
+    hc = HostColumn.from_values(np.arange(5000, dtype=np.uint32) % 300, "ppvbs")
+    try:
+        used = [s for s in range(_lib.NBUF) if hc.info.bytes[s]]
+        assert used
+        ptrs = [0] * _lib.NBUF
+        ptrs[used[0]] = 0x10008   # 8-byte aligned only
+        with pytest.raises(RuntimeError, match="16-byte aligned"):
+            _lib.bst_upload(hc.h, ptrs, 0)
+    finally:
+        hc.close()
