@@ -1106,6 +1106,15 @@ def main():
     main_lay = "ppvbs" if "ppvbs" in res else layouts[0]
     r = res[main_lay]
     traffic = read_traffic()
+    # the streaming probe on the same BS_1: the traffic of a scan settled by byte 1
+    # without the compares, in the scans' launch shape -- the rate such a scan can
+    # reach here (untimed steps; its own HIP events)
+    bs1 = cols[main_lay][1].bufs[_lib.BUF_BS1]
+    probe_out = torch.empty(bs1.numel() // 8, dtype=torch.uint8, device="cuda")
+    probe_ms = _ms_events(lambda: _lib.bst_stream_probe(bs1, bs1.numel(), probe_out,
+                                                        torch.cuda.current_stream().cuda_stream))
+    probe_gbs = (bs1.numel() + probe_out.numel()) / (probe_ms * 1e-3) / 1e9
+    del probe_out
     roofline = {
         "bound": "hbm",
         "achieved": round(r["alg_gbs"], 1),
@@ -1116,6 +1125,11 @@ def main():
         "kernel": "k_scan_slices (PP-VBS)",
         "alg_bytes_per_launch": r["alg_bytes_per_launch"],
         "avg_launch_ms": float(np.mean(r["scan_ms"])),
+        # HBM bytes moved per second (counter traffic / launch time), and the
+        # streaming probe's rate on the same bytes' shape: how close the scan's
+        # actual traffic runs to what this chip streams
+        "traffic_gbs": None if traffic is None else round(traffic / (np.mean(r["scan_ms"]) * 1e-3) / 1e9, 1),
+        "probe_gbs": round(probe_gbs, 1),
     }
     lookup_roofline = None
     if not args.no_lookup:

@@ -364,6 +364,19 @@ int bst_batch_launch(bst_batch* b, uint32_t grid, uint32_t tiles_per_grab, int u
                      void* stream);
 void bst_batch_free(bst_batch* b);
 
+/* ---- measurement ------------------------------------------------------- */
+/*
+ * Streaming probe, a measurement aid rather than an operation of the paper:
+ * read `bytes` of `src` (a multiple of 2048) in 2048-byte tiles and write
+ * bytes/8 to `dst` (both device memory, 16-byte aligned), with the launch
+ * shape, tile layout and cache policies of the slice scans.  That is the
+ * traffic of a scan in which byte 1 settles every row (Sec. 3.3's early stop
+ * at its best) without the compares, so its rate bounds what such a scan can
+ * reach on this chip.  Errors: BST_EINVAL for a NULL pointer, a size that is
+ * not a multiple of 2048 or a misaligned buffer.
+ */
+int bst_stream_probe(const void* src, uint64_t bytes, void* dst, void* stream);
+
 /* ---- launch tuning ----------------------------------------------------- */
 enum {
     BST_TUNE_SCAN_GRID = 0,    /* workgroups of a single-column scan launch (0 = auto) */

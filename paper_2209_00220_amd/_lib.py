@@ -94,6 +94,7 @@ _PROTOS = {
     "bst_auc": (_I, [_P, _P, _I, _P]),
     "bst_choose": (_I, [_P, _P, _I, _P]),
     "bst_advise": (_I, [_P, _I, _I, _P, _P, _I, _I, _P, _P, _P, _P, _P]),
+    "bst_stream_probe": (_I, [_P, _U64, _P, _P]),
     "bst_batch_workspace_bytes": (_U64, [_I]),
     "bst_batch_prepare": (_I, [_P, _P, _P, _P, _I, _P, _P]),
     "bst_batch_launch": (_I, [_P, _U32, _U32, _I, _P]),
@@ -364,6 +365,10 @@ def bst_batch_launch(b, grid: int, tiles_per_grab: int, use_graph: bool, stream:
 
 def bst_batch_free(b):
     lib().bst_batch_free(b)
+
+
+def bst_stream_probe(src, nbytes: int, dst, stream: int):
+    _call("bst_stream_probe", _ptr(src), nbytes, _ptr(dst), stream)
 
 
 def bst_tune_set(key: int, value: int):

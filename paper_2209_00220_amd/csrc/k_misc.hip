@@ -43,6 +43,35 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     return v;
 }
 
+// The traffic of a scan that settles every row on its first byte, without the
+// compares: a wave reads 2048-byte tiles (two 16-byte loads per lane, the
+// layout and cache policy of BS_1), the next tile's loads in flight while the
+// current one is folded, and stores one dword per lane (the tile's 256-byte
+// result) non-temporally; grid-stride over the tiles with the scans' launch
+// shape.
+__global__ __launch_bounds__(kBlock) void k_stream_probe(const uint8_t* __restrict__ src, uint64_t ntiles,
+                                                         uint32_t* __restrict__ dst) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t wave = uniform(blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6));
+    const uint64_t nwaves = (uint64_t)gridDim.x * kWavesPerBlock;
+    auto load = [&](uint64_t t, uint4& a, uint4& b) {
+        // a tile past the end reads as zeros (an empty buffer range)
+        const auto r = buffer_rsrc(src + (t < ntiles ? t : 0) * kTileRows, t < ntiles ? (uint32_t)kTileRows : 0u);
+        a = buffer_load16(r, lane * 16);
+        b = buffer_load16(r, 1024 + lane * 16);
+    };
+    uint4 a, b;
+    load(wave, a, b);
+    for (uint64_t t = wave; t < ntiles; t += nwaves) {
+        uint4 na, nb;
+        load(t + nwaves, na, nb);
+        const uint32_t v = a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w;
+        __builtin_nontemporal_store(v, dst + t * 64 + lane);
+        a = na;
+        b = nb;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_bv_popcount(const uint64_t* __restrict__ bv, uint64_t n,
                                                         unsigned long long* __restrict__ count) {
     __shared__ uint32_t part[kWavesPerBlock];
@@ -560,6 +589,19 @@ int bst_bv_popcount(const uint64_t* bv, uint64_t n_rows, uint64_t* dev_count, vo
                            dim3(kBlock), 0, st, bv, n_rows,
                            (unsigned long long*)dev_count);
     return hip_check(hipGetLastError(), "popcount launch");
+}
+
+// ---- streaming probe ---------------------------------------------------------
+int bst_stream_probe(const void* src, uint64_t bytes, void* dst, void* stream) {
+    if (!src || !dst) return set_error(BST_EINVAL, "NULL argument");
+    if (bytes % kTileRows) return set_error(BST_EINVAL, "probe size must be a multiple of 2048 bytes");
+    if (reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+        return set_error(BST_EINVAL, "probe buffers must be 16-byte aligned");
+    const uint64_t ntiles = bytes / kTileRows;
+    if (!ntiles) return BST_OK;
+    hipLaunchKernelGGL(k_stream_probe, dim3(tile_grid(ntiles, g_tune[BST_TUNE_SCAN_GRID])), dim3(kBlock), 0,
+                       (hipStream_t)stream, (const uint8_t*)src, ntiles, (uint32_t*)dst);
+    return hip_check(hipGetLastError(), "probe launch");
 }
 
 // ---- advisor -------------------------------------------------------------

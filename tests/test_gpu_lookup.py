@@ -26,6 +26,28 @@ def _np32(t):
     return u32_to_numpy(t)
 
 
+@pytest.mark.parametrize("dir_stride", [64, 128, 256, 512, 1024, 2048])
+def test_lookup_every_directory_stride(dir_stride):
+    """PP-VBS lookups of every row at each directory stride: one mask word per
+    block (64), blocks read as 16-byte pairs (128..512), and the per-word walk
+    (1024, 2048); codes of up to five bytes from the sorted mapping, a ragged
+    tail, rows at every position of a block."""
+    from paper_2209_00220_amd.column import u32_from_numpy
+
+    n = 70_001
+    flush("lookup every row, dir_stride=%d" % dir_stride)
+    x = datagen.zipf_column(n, 16, 1.0, seed=11, mapping=datagen.SORTED)
+    cols = device_columns(x, 16, layouts=("ppvbs",), dir_stride=dir_stride)
+    try:
+        hc, col = cols["ppvbs"]
+        assert hc.info.k_max >= 3
+        ids = np.arange(n, dtype=np.uint32)
+        got = _np32(col.lookup(u32_from_numpy(ids)))
+        assert np.array_equal(got, lookup_ids(x, ids))
+    finally:
+        close_columns(cols)
+
+
 @pytest.mark.parametrize("n,w,s,mapping", [
     (1, 12, 1.0, datagen.SCATTER), (65, 12, 1.0, datagen.SCATTER), (4097, 20, 1.0, datagen.SORTED),
     (300_007, 20, 1.0, datagen.SCATTER), (2_000_003, 20, 0.5, datagen.SORTED), (200_000, 32, 0.0, datagen.SCATTER),
