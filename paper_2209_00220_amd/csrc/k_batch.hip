@@ -201,7 +201,29 @@ struct bst_batch {
     uint32_t graph_grid = 0, graph_grab = 0;
     int64_t graph_streams = 0;
     hipStream_t graph_stream = nullptr;
+    // fork and join events of the captured graph: its own, made before its
+    // capture and destroyed after it, never shared with eager launches or other
+    // graphs
+    std::vector<hipEvent_t> graph_events;
 };
+
+// Streams a batch's launches are spread over: the tuned count, at most one per
+// unit of work (group launch or solo item).
+static int batch_streams(const bst_batch* b) {
+    const uint64_t n_units = b->groups.size() + b->solo.size();
+    return (int)std::max<uint64_t>(
+        1, std::min<uint64_t>(n_units, (uint64_t)std::max<int64_t>(
+                                           1, std::min<int64_t>(g_tune[BST_TUNE_BATCH_STREAMS], kBatchStreamsMax))));
+}
+
+static void destroy_graph(bst_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    for (hipEvent_t e : b->graph_events) (void)hipEventDestroy(e);
+    b->graph_events.clear();
+}
 
 extern "C" {
 
@@ -286,7 +308,9 @@ int bst_batch_prepare(const bst_column* const* cols, const bst_pred* preds, cons
     return BST_OK;
 }
 
-static int batch_enqueue(bst_batch* b, uint32_t grid, uint32_t grab, hipStream_t st) {
+// Enqueue the batch on `st`.  events: the fork event and ns - 1 join events to
+// use (a graph capture brings its own), or nullptr for the device's shared set.
+static int batch_enqueue(bst_batch* b, uint32_t grid, uint32_t grab, hipStream_t st, const hipEvent_t* events) {
     char* ws = (char*)b->ws;
     const BatchItem* items = (const BatchItem*)(ws + (uint64_t)kBatchGroupsMax * kBatchHeaderBytes);
     for (size_t i = 0; i < b->fills.size(); ++i) {
@@ -301,16 +325,19 @@ static int batch_enqueue(bst_batch* b, uint32_t grid, uint32_t grab, hipStream_t
     // Units go to the least loaded of `ns` streams, largest first: a group that
     // cannot fill the chip, and the tail of each launch, overlap with other
     // units instead of idling the device.
-    const int ns = (int)std::min<uint64_t>(n_units, std::max<int64_t>(1, std::min<int64_t>(g_tune[BST_TUNE_BATCH_STREAMS],
-                                                                                          kBatchStreamsMax)));
+    const int ns = batch_streams(b);
     ForkSet* fs = nullptr;
     hipStream_t lanes[kBatchStreamsMax] = {st};
+    hipEvent_t fork = nullptr, join[kBatchStreamsMax - 1] = {};
     if (ns > 1) {
         int rc = fork_set(&fs);
-        if (!rc) rc = hip_check(hipEventRecord(fs->fork, st), "batch fork");
+        if (rc) return rc;
+        fork = events ? events[0] : fs->fork;
+        for (int i = 1; i < ns; ++i) join[i - 1] = events ? events[i] : fs->join[i - 1];
+        rc = hip_check(hipEventRecord(fork, st), "batch fork");
         for (int i = 1; !rc && i < ns; ++i) {
             lanes[i] = fs->helper[i - 1];
-            rc = hip_check(hipStreamWaitEvent(lanes[i], fs->fork, 0), "batch fork");
+            rc = hip_check(hipStreamWaitEvent(lanes[i], fork, 0), "batch fork");
         }
         if (rc) return rc;
     }
@@ -363,8 +390,8 @@ static int batch_enqueue(bst_batch* b, uint32_t grid, uint32_t grab, hipStream_t
         if (!rc) rc = r;
     }
     for (int i = 1; i < ns; ++i) {   // join every helper back, also after an error
-        int r2 = hip_check(hipEventRecord(fs->join[i - 1], lanes[i]), "batch join");
-        if (!r2) r2 = hip_check(hipStreamWaitEvent(st, fs->join[i - 1], 0), "batch join");
+        int r2 = hip_check(hipEventRecord(join[i - 1], lanes[i]), "batch join");
+        if (!r2) r2 = hip_check(hipStreamWaitEvent(st, join[i - 1], 0), "batch join");
         if (!rc) rc = r2;
     }
     return rc;
@@ -388,19 +415,24 @@ int bst_batch_launch(bst_batch* b, uint32_t grid, uint32_t tiles_per_grab, int u
         if (rc) return rc;
         b->uploaded = true;
     }
-    if (!use_graph) return batch_enqueue(b, grid, tiles_per_grab, st);
+    if (!use_graph) return batch_enqueue(b, grid, tiles_per_grab, st, nullptr);
     if (!b->exec || b->graph_grid != grid || b->graph_grab != tiles_per_grab ||
         b->graph_streams != g_tune[BST_TUNE_BATCH_STREAMS]) {
-        if (b->exec) (void)hipGraphExecDestroy(b->exec);
-        if (b->graph) (void)hipGraphDestroy(b->graph);
-        b->exec = nullptr;
-        b->graph = nullptr;
+        destroy_graph(b);
+        // the graph's own fork and join events, made before the capture starts
+        const int ns = batch_streams(b);
+        for (int i = 0; ns > 1 && i < ns; ++i) {
+            hipEvent_t e;
+            int rc = hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "graph event");
+            if (rc) return rc;
+            b->graph_events.push_back(e);
+        }
         hipStream_t cap;
         int rc = hip_check(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "capture stream");
         if (rc) return rc;
         rc = hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "begin capture");
         if (!rc) {
-            int rc2 = batch_enqueue(b, grid, tiles_per_grab, cap);
+            int rc2 = batch_enqueue(b, grid, tiles_per_grab, cap, b->graph_events.empty() ? nullptr : b->graph_events.data());
             rc = hip_check(hipStreamEndCapture(cap, &b->graph), "end capture");
             if (!rc) rc = rc2;
         }
@@ -416,8 +448,7 @@ int bst_batch_launch(bst_batch* b, uint32_t grid, uint32_t tiles_per_grab, int u
 
 void bst_batch_free(bst_batch* b) {
     if (!b) return;
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
+    destroy_graph(b);
     delete b;
 }
 
