@@ -79,3 +79,15 @@ def test_upload_rejects_misaligned_buffers(built_lib):
             _lib.bst_upload(hc.h, ptrs, 0)
     finally:
         hc.close()
+
+
+def test_probe_arguments_checked_before_any_launch(built_lib):
+    """The streaming probe validates its arguments on the host (no GPU needed)."""
+    from paper_2209_00220_amd import _lib
+
+    with pytest.raises(RuntimeError, match="NULL"):
+        _lib.bst_stream_probe(0, 2048, 0x10000, 0)
+    with pytest.raises(RuntimeError, match="multiple of 2048"):
+        _lib.bst_stream_probe(0x10000, 1000, 0x20000, 0)
+    with pytest.raises(RuntimeError, match="aligned"):
+        _lib.bst_stream_probe(0x10008, 2048, 0x20000, 0)
