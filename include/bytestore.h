@@ -353,8 +353,10 @@ int bst_batch_prepare(const bst_column* const* cols, const bst_pred* preds,
  * BST_TUNE_BATCH_STREAMS = s > 1 the launches are spread over s streams (largest
  * first, to the least loaded): helper streams of the library fork off
  * `stream` after the counter reset and join back into it before the call
- * returns, so later work on `stream` still sees every result.  The items must
- * be independent (no item's incoming mask is another item's output).  With
+ * returns, so later work on `stream` still sees every result; such launches
+ * (and captures) from several host threads on one device take turns on the
+ * helper streams.  The items must be independent (no item's incoming mask is
+ * another item's output).  With
  * use_graph != 0 the launch sequence is captured once into a HIP graph (the
  * streams become parallel branches) and replayed on later calls with the same
  * grid, grab size and stream count.  Errors: BST_EINVAL for a NULL batch,
@@ -397,6 +399,10 @@ enum {
                                   persistent group launch                          */
     BST_TUNE_NKEYS = 7
 };
+/* Tuning values are process-wide, read when a launch is enqueued (the solo
+ * threshold when a batch is prepared); set them while no other host thread
+ * launches.  bst_tune_set: BST_EINVAL for an unknown key or a value out of
+ * range; bst_tune_get: -1 for an unknown key. */
 int bst_tune_set(int key, int64_t value);
 int64_t bst_tune_get(int key);
 

@@ -155,6 +155,7 @@ struct ForkSet {
     hipEvent_t fork = nullptr;
     hipEvent_t join[kBatchStreamsMax - 1] = {};
     bool ready = false;
+    std::mutex use;   // held from the fork to the join: one batch on the helpers at a time
 };
 
 int fork_set(ForkSet** out) {
@@ -329,9 +330,11 @@ static int batch_enqueue(bst_batch* b, uint32_t grid, uint32_t grab, hipStream_t
     ForkSet* fs = nullptr;
     hipStream_t lanes[kBatchStreamsMax] = {st};
     hipEvent_t fork = nullptr, join[kBatchStreamsMax - 1] = {};
+    std::unique_lock<std::mutex> hold;   // the device's helper streams, until they are joined back
     if (ns > 1) {
         int rc = fork_set(&fs);
         if (rc) return rc;
+        hold = std::unique_lock<std::mutex>(fs->use);
         fork = events ? events[0] : fs->fork;
         for (int i = 1; i < ns; ++i) join[i - 1] = events ? events[i] : fs->join[i - 1];
         rc = hip_check(hipEventRecord(fork, st), "batch fork");
