@@ -1105,16 +1105,20 @@ def main():
 
     main_lay = "ppvbs" if "ppvbs" in res else layouts[0]
     r = res[main_lay]
-    traffic = read_traffic()
+    lay_name = {"ppvbs": "PP-VBS", "byteslice": "ByteSlice", "bitpacked": "Bit-Packed"}[main_lay]
+    # the committed counter summary covers the PP-VBS launches
+    traffic = read_traffic() if main_lay == "ppvbs" else None
     # the streaming probe on the same BS_1: the traffic of a scan settled by byte 1
     # without the compares, in the scans' launch shape -- the rate such a scan can
     # reach here (untimed steps; its own HIP events)
-    bs1 = cols[main_lay][1].bufs[_lib.BUF_BS1]
-    probe_out = torch.empty(bs1.numel() // 8, dtype=torch.uint8, device="cuda")
-    probe_ms = _ms_events(lambda: _lib.bst_stream_probe(bs1, bs1.numel(), probe_out,
-                                                        torch.cuda.current_stream().cuda_stream))
-    probe_gbs = (bs1.numel() + probe_out.numel()) / (probe_ms * 1e-3) / 1e9
-    del probe_out
+    bs1 = cols[main_lay][1].bufs[_lib.BUF_BS1]   # None for a Bit-Packed column
+    probe_gbs = None
+    if bs1 is not None:
+        probe_out = torch.empty(bs1.numel() // 8, dtype=torch.uint8, device="cuda")
+        probe_ms = _ms_events(lambda: _lib.bst_stream_probe(bs1, bs1.numel(), probe_out,
+                                                            torch.cuda.current_stream().cuda_stream))
+        probe_gbs = (bs1.numel() + probe_out.numel()) / (probe_ms * 1e-3) / 1e9
+        del probe_out
     roofline = {
         "bound": "hbm",
         "achieved": round(r["alg_gbs"], 1),
@@ -1122,14 +1126,14 @@ def main():
         "unit": "GB/s",
         "frac": round(r["alg_gbs"] / HBM_PEAK_GBS, 4),
         "traffic": traffic,
-        "kernel": "k_scan_slices (PP-VBS)",
+        "kernel": "%s (%s)" % ("k_scan_packed" if main_lay == "bitpacked" else "k_scan_slices", lay_name),
         "alg_bytes_per_launch": r["alg_bytes_per_launch"],
         "avg_launch_ms": float(np.mean(r["scan_ms"])),
         # HBM bytes moved per second (counter traffic / launch time), and the
         # streaming probe's rate on the same bytes' shape: how close the scan's
         # actual traffic runs to what this chip streams
         "traffic_gbs": None if traffic is None else round(traffic / (np.mean(r["scan_ms"]) * 1e-3) / 1e9, 1),
-        "probe_gbs": round(probe_gbs, 1),
+        "probe_gbs": None if probe_gbs is None else round(probe_gbs, 1),
     }
     lookup_roofline = None
     if not args.no_lookup:
@@ -1140,8 +1144,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(lk_gbs / HBM_PEAK_GBS, 4),
-            "traffic": read_traffic("lookup_hbm_bytes_per_launch"),
-            "kernel": "k_lookup (PP-VBS)",
+            "traffic": read_traffic("lookup_hbm_bytes_per_launch") if main_lay == "ppvbs" else None,
+            "kernel": "k_lookup (%s)" % lay_name,
             "alg_bytes_per_id": round(r["lookup_alg_bytes_per_id"], 1),
             "ids_per_launch": int(ids.shape[0]),
             "avg_launch_ms": r["lookup_ms"],
