@@ -116,16 +116,15 @@ def lookup_alg_bytes_per_id(info) -> float:
     """Algorithmic bytes of one lookup by row ID: the 4-byte ID and 4-byte value,
     plus one 128-byte line per random access the layout needs.  PP-VBS: BS_1;
     then, per later byte j <= L(r), the M_j word, the directory entry and the
-    BS_j byte; and the M_{L+1} word that shows the code ends (when L < K).
-    ByteSlice: one line per slice.  Bit-Packed: one line, two when the code
+    BS_j byte; and the M_{L+1} word that shows the code ends, for the rows whose
+    length no decode-table leaf fixes (rows_end_by_mask).  ByteSlice: one line per slice.  Bit-Packed: one line, two when the code
     straddles two dwords.  Decode tables (trie, dictionary) are not counted."""
     K = int(info.k_max)
     if info.layout == 2:   # PP-VBS
         n = float(info.n_rows) or 1.0
         lines = 0.0
         for L in range(1, K + 1):
-            f = info.rows_by_len[L] / n
-            lines += f * (1 + 3 * (L - 1) + (1 if L < K else 0))
+            lines += (info.rows_by_len[L] * (1 + 3 * (L - 1)) + info.rows_end_by_mask[L]) / n
     elif info.layout == 1:
         lines = float(K)
     else:

@@ -112,6 +112,10 @@ typedef struct {
     uint64_t rows_by_len[BST_KMAX + 1]; /* PP-VBS: rows whose code has exactly j bytes */
     uint64_t layout_bytes;             /* bytes of the layout proper (slices, masks,
                                           directories, packed words)                */
+    uint64_t rows_end_by_mask[BST_KMAX + 1]; /* PP-VBS: of rows_by_len[j] (j < k_max),
+                                          the rows whose code length a lookup learns
+                                          only by reading M_{j+1}; the others end in
+                                          a decode-table leaf that fixes the length */
 } bst_column_info;
 
 /* ---- diagnostics -------------------------------------------------------- */

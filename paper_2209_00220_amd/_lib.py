@@ -47,6 +47,7 @@ class ColumnInfo(ctypes.Structure):
         ("n_rows", ctypes.c_uint64), ("n_distinct", ctypes.c_uint64),
         ("bytes", ctypes.c_uint64 * NBUF), ("total_bytes", ctypes.c_uint64),
         ("rows_by_len", ctypes.c_uint64 * (KMAX + 1)), ("layout_bytes", ctypes.c_uint64),
+        ("rows_end_by_mask", ctypes.c_uint64 * (KMAX + 1)),
     ]
 
 

@@ -274,13 +274,18 @@ __device__ __forceinline__ void scan_packed_range(const DevCol& c, const PackedL
 // its own; the decode tables walk Algorithm 1's tree: a slot ends the code (and
 // holds its value), a pointer descends, a leaf turns the remaining bytes into a
 // slot number (a rank into the dictionary).
+// Base rank of a leaf entry (its low bits; the slot digits, when stored, sit above).
+__device__ __forceinline__ uint32_t leaf_base(const DevCol& c, uint32_t ch) {
+    return ch & (c.leaf_digits ? ((1u << kLeafDigitsShift) - 1u) : ~kLeafFlag);
+}
+
 __device__ __forceinline__ uint32_t trie_value(const DevCol& c, uint64_t code, uint32_t len) {
     uint32_t ch = c.trie_root;
     for (uint32_t j = 1;; ++j) {
         if (ch & kLeafFlag) {   // a leaf: the remaining bytes number a slot of consecutive ranks
             const uint32_t rest = len - j + 1;
             const uint64_t slot = rest >= 8 ? code : (code & ((1ull << (8 * rest)) - 1));
-            return c.dict[(ch & ~kLeafFlag) + (uint32_t)slot - 1u];
+            return c.dict[leaf_base(c, ch) + (uint32_t)slot - 1u];
         }
         const uint32_t byte = (uint32_t)(code >> (8 * (len - j))) & 0xffu;
         const uint32_t* e = c.trie + ((uint64_t)ch * 256 + byte) * 2;
@@ -308,10 +313,23 @@ __device__ __forceinline__ uint32_t lookup_row(const DevCol& c, uint64_t r) {
         const uint64_t g = r >> 6;
         const uint64_t below = (1ull << (r & 63)) - 1;
         const uint32_t lw = c.dir_shift - 6;
+        // Once the code's prefix leads into a leaf of the decode trie, the leaf's
+        // slot digits give the code's length, and the mask that would show the
+        // code ends (M_{L+1}) need not be read.  `node`: the trie node of the next
+        // digit to consume (a leaf entry once known), `known`: the length, or 0.
+        const bool guided = c.leaf_digits && !c.categorical;
+        uint32_t node = c.trie_root, known = 0;
+        if (guided && (node & kLeafFlag)) known = (node >> kLeafDigitsShift) & 7u;
         for (uint32_t j = 2; j <= c.K; ++j) {
+            if (known && j > known) break;
             uint64_t before;
             const uint64_t w = vbs_word(c, j, g, before);
             if (!((w >> (r & 63)) & 1)) break;
+            if (guided && !known) {
+                // the code goes on past byte j - 1: follow that digit's child
+                node = c.trie[((uint64_t)node * 256 + (uint32_t)(code & 0xffu)) * 2 + 1];
+                if (node & kLeafFlag) known = (j - 1) + ((node >> kLeafDigitsShift) & 7u);
+            }
             const uint64_t off = c.dir[j][g >> lw] + before + __builtin_popcountll(w & below);
             code = (code << 8) | c.bs[j][off];
             len = j;

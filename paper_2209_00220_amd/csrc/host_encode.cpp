@@ -178,6 +178,7 @@ struct PpeBuilder {
     std::vector<uint32_t>& trie;   // 512 uint32 per node: (slot rank, child) x 256; the
                                    // encoder replaces each slot rank by the slot's value
     std::vector<uint32_t> idx;     // scratch for the top-255 selection
+    bool leaf_digits = false;      // leaf entries also carry their slot digits
 
     static uint32_t digits(uint64_t count) {   // smallest beta with 256^beta >= count
         uint32_t beta = 0;
@@ -200,7 +201,9 @@ struct PpeBuilder {
                 C[i] = (beta ? (C[i] << (8 * beta)) : C[i]) + 1 + (i - s);
                 L[i] = (uint8_t)(b + beta);
             }
-            return kLeafFlag | (uint32_t)s;
+            // a leaf: base rank s, and (when it fits) the digits of its slot
+            // numbers, which fix the length of every code below it
+            return kLeafFlag | (uint32_t)s | (leaf_digits ? beta << kLeafDigitsShift : 0u);
         }
         uint32_t node = (uint32_t)(trie.size() / 512);
         trie.resize(trie.size() + 512, 0);
@@ -284,6 +287,8 @@ static void build_vbs(HostColumn& c, const uint32_t* rank, uint32_t T) {
     }
     for (uint32_t j = 1; j <= BST_KMAX; ++j) c.rows_by_len[j] = tot[j] - (j < BST_KMAX ? tot[j + 1] : 0);
     c.rows_by_len[0] = 0;
+    // without length-carrying decode leaves, every code shorter than K ends at a 0 in M_{len+1}
+    for (uint32_t j = 0; j <= BST_KMAX; ++j) c.rows_end_by_mask[j] = j < K ? c.rows_by_len[j] : 0;
     for (uint32_t j = 2; j <= K; ++j) c.buf[BST_BUF_BS2 + j - 2].assign(tot[j] + 64, 0);
     // pass 2: bytes, masks, directories
     parallel_chunks(n, parts, kTileRows, [&](uint64_t lo, uint64_t hi, uint32_t t) {
@@ -443,8 +448,9 @@ static int encode_column(const Dict& d, int layout, uint32_t width, uint32_t dir
         c.code.assign(c.nd, 0);
         c.clen.assign(c.nd, 0);
         std::vector<uint32_t> trie;
-        PpeBuilder pb{d.Q, c.code, c.clen, trie, {}};
+        PpeBuilder pb{d.Q, c.code, c.clen, trie, {}, c.nd < kLeafDigitsMaxValues};
         c.trie_root = pb.encode(0, 0, c.nd);
+        c.leaf_digits = pb.leaf_digits ? 1u : 0u;
         uint32_t K = 1;
         for (uint8_t l : c.clen) K = std::max<uint32_t>(K, l);
         if (K > BST_KMAX) return set_error(BST_ERANGE, "code longer than BST_KMAX bytes");
@@ -452,13 +458,23 @@ static int encode_column(const Dict& d, int layout, uint32_t width, uint32_t dir
         c.width = 8 * K;
         c.buf[BST_BUF_DICT].resize(c.nd * 4);
         if (c.nd) memcpy(c.buf[BST_BUF_DICT].data(), c.dict.data(), c.nd * 4);
+        // codes that end in a slot: only for them does a lookup read M_{len+1} to see
+        // the code end (a leaf entry carries the length of the codes below it)
+        std::vector<uint8_t> in_slot(c.nd, 0);
+        for (size_t k = 0; k < trie.size(); k += 2)
+            if (k % 512 != 0) in_slot[trie[k]] = 1;
+        c.buf[BST_BUF_TRIE].resize(trie.size() * 4);
+        build_vbs(c, d.rank.data(), T);
+        if (c.leaf_digits) {
+            for (uint32_t j = 0; j <= BST_KMAX; ++j) c.rows_end_by_mask[j] = 0;
+            for (uint64_t i = 0; i < c.nd; ++i)
+                if (in_slot[i] && c.clen[i] < K) c.rows_end_by_mask[c.clen[i]] += d.Q[i];
+        }
         // slot entries carry the slot's value rather than its rank, so a lookup of
         // a code that ends in a slot needs no dictionary read
         for (size_t k = 0; k < trie.size(); k += 2)
             if (k % 512 != 0) trie[k] = c.dict[trie[k]];
-        c.buf[BST_BUF_TRIE].resize(trie.size() * 4);
         if (!trie.empty()) memcpy(c.buf[BST_BUF_TRIE].data(), trie.data(), trie.size() * 4);
-        build_vbs(c, d.rank.data(), T);
         return BST_OK;
     }
     // fixed-length codes
@@ -765,6 +781,7 @@ int bst_host_info(const bst_host_column* hc, bst_column_info* info) {
         if (s != BST_BUF_DICT && s != BST_BUF_TRIE) info->layout_bytes += c.buf[s].size();
     }
     for (int j = 0; j <= BST_KMAX; ++j) info->rows_by_len[j] = c.rows_by_len[j];
+    for (int j = 0; j <= BST_KMAX; ++j) info->rows_end_by_mask[j] = c.rows_end_by_mask[j];
     return BST_OK;
 }
 

@@ -13,6 +13,10 @@ namespace bst {
 constexpr uint32_t kTileRows = BST_TILE_ROWS;   // rows per tile (32 groups of 64)
 constexpr uint32_t kGroupsPerTile = kTileRows / 64;
 constexpr uint32_t kLeafFlag = 0x80000000u;     // decode-table child entry is a leaf
+// With fewer than 2^28 distinct values a leaf entry also carries, in bits 28-30,
+// the digits its slot numbers take (so the length of every code below it).
+constexpr uint32_t kLeafDigitsShift = 28;
+constexpr uint64_t kLeafDigitsMaxValues = 1ull << 28;
 constexpr uint32_t kDefaultDirStride = 512;
 
 // Error reporting (thread-local message behind bst_last_error()).
@@ -36,7 +40,9 @@ struct HostColumn {
     std::vector<uint8_t> clen;       // per distinct value: code length in bytes
     std::vector<uint8_t> buf[BST_NBUF];
     uint64_t rows_by_len[BST_KMAX + 1] = {0};
+    uint64_t rows_end_by_mask[BST_KMAX + 1] = {0};   // rows whose lookup reads M_{len+1}
     uint32_t trie_root = kLeafFlag;
+    uint32_t leaf_digits = 0;        // leaf entries carry their slot digits (kLeafDigitsShift)
 };
 
 // A literal in code space as the kernels take it.
@@ -73,7 +79,8 @@ int code_literal(const HostColumn& c, int op, uint64_t lo, uint32_t llo, uint64_
 struct DevCol {
     uint32_t layout, width, K, dir_shift;
     uint32_t domain_mode, trie_root;
-    uint32_t categorical, pad0;          // Algorithm 2 codes: decode arithmetically, dict by frequency
+    uint32_t categorical;                // Algorithm 2 codes: decode arithmetically, dict by frequency
+    uint32_t leaf_digits;                // trie leaf entries carry their slot digits
     uint64_t n, ntiles;
     const uint8_t* bs[BST_KMAX + 1];     // bs[1..K]
     const uint64_t* m[BST_KMAX + 1];     // m[2..K]

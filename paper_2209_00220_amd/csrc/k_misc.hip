@@ -349,7 +349,7 @@ int bst_upload(const bst_host_column* hc, void* const dev_bufs[BST_NBUF], void* 
     c.domain_mode = h.domain_mode;
     c.trie_root = h.trie_root;
     c.categorical = h.categorical;
-    c.pad0 = 0;
+    c.leaf_digits = h.leaf_digits;
     c.n = h.n;
     c.ntiles = h.ntiles;
     c.bs[1] = (const uint8_t*)dev_bufs[BST_BUF_BS1];

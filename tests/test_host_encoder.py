@@ -31,6 +31,27 @@ def _columns():
     yield "gauss20", datagen.gaussian_column(200_000, 20, 2.0 ** 10, seed=8)
 
 
+def _rows_end_by_mask(C, Lc, Q):
+    """Rows whose code ends in a slot of an internal node of Algorithm 1's tree,
+    per code length below K, read off the codes alone: the root is internal once
+    a code is longer than one byte, so every 1-byte code is then a root slot; the
+    values under root pointer t (codes longer than one byte with first digit t)
+    get an internal node of their own when there are 256 or more of them, and its
+    slots are exactly their 2-byte codes (fewer take 2-byte slot numbers of a
+    leaf); past the depth cut every code ends in a leaf."""
+    K = int(Lc.max())
+    out = [0] * 7
+    if K == 1:
+        return out
+    out[1] = int(Q[Lc == 1].sum())
+    if K > 2:
+        first = (C >> ((Lc - 1) * 8).astype(np.uint64)).astype(np.int64)
+        under = np.bincount(first[Lc >= 2], minlength=256)
+        two = Lc == 2
+        out[2] = int(Q[two & (under[first] >= 256)].sum())
+    return out
+
+
 @pytest.mark.parametrize("name,x", list(_columns()), ids=[c[0] for c in _columns()])
 def test_dictionary_and_ppe_codes(L, name, x):
     A, Q, rank = build_dictionary(x)
@@ -55,6 +76,7 @@ def test_dictionary_and_ppe_codes(L, name, x):
                 assert np.array_equal(L.bst_host_paper_view(h, 1, j).view(np.uint64), pack_bits(M[j])), (name, j)
             by_len = np.bincount(Lc[rank], minlength=7)
             assert [int(info.rows_by_len[j]) for j in range(1, 7)] == [int(v) for v in by_len[1:7]]
+            assert [int(info.rows_end_by_mask[j]) for j in range(7)] == _rows_end_by_mask(C, Lc, Q)
         finally:
             L.bst_free_host(h)
     finally:
