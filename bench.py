@@ -1133,6 +1133,11 @@ def main():
         # actual traffic runs to what this chip streams
         "traffic_gbs": None if traffic is None else round(traffic / (np.mean(r["scan_ms"]) * 1e-3) / 1e9, 1),
         "probe_gbs": None if probe_gbs is None else round(probe_gbs, 1),
+        # the bytes a scan without early stop would read (every row's whole code,
+        # the result and any incoming mask) over the same launch time: the rate
+        # at which the column's codes are evaluated, against the same peak
+        "full_scan_gbs": round(r["full_bytes_per_launch"] / (np.mean(r["scan_ms"]) * 1e-3) / 1e9, 1),
+        "full_scan_frac": round(r["full_bytes_per_launch"] / (np.mean(r["scan_ms"]) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
     lookup_roofline = None
     if not args.no_lookup:
