@@ -151,15 +151,32 @@ static int build_dict(const uint32_t* x, uint64_t n, uint32_t T, Dict& d) {
     }
     tmp.clear();
     tmp.shrink_to_fit();
+    {
+        uint64_t total = 0;
+        for (int b = 0; b < 256; ++b) total += uv[b].size();
+        d.A.reserve(total);
+        d.Q.reserve(total);
+    }
     for (int b = 0; b < 256; ++b) {
         d.A.insert(d.A.end(), uv[b].begin(), uv[b].end());
         d.Q.insert(d.Q.end(), uc[b].begin(), uc[b].end());
+        std::vector<uint32_t>().swap(uv[b]);
+        std::vector<uint64_t>().swap(uc[b]);
     }
+    // ranks: a directory over the top 24 bits narrows each search to the entries
+    // that share them (first[p] = entries below p << 8; nd < 2^32), so it stays
+    // in a cache line or two instead of walking the whole sorted array
     const uint32_t* A = d.A.data();
-    uint64_t nd = d.A.size();
+    const uint64_t nd = d.A.size();
+    constexpr int kDirShift = 8;
+    std::vector<uint32_t> first((1u << (32 - kDirShift)) + 1, (uint32_t)nd);
+    for (uint64_t k = nd; k-- > 0;) first[A[k] >> kDirShift] = (uint32_t)k;
+    for (uint64_t p = first.size() - 1; p-- > 0;) first[p] = std::min(first[p], first[p + 1]);
     parallel_chunks(n, T, 1 << 16, [&](uint64_t lo, uint64_t hi, uint32_t) {
-        for (uint64_t i = lo; i < hi; ++i)
-            d.rank[i] = (uint32_t)(std::lower_bound(A, A + nd, x[i]) - A);
+        for (uint64_t i = lo; i < hi; ++i) {
+            const uint32_t p = x[i] >> kDirShift;
+            d.rank[i] = (uint32_t)(std::lower_bound(A + first[p], A + first[p + 1], x[i]) - A);
+        }
     });
     return BST_OK;
 }
