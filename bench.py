@@ -726,10 +726,11 @@ def batch_main(args):
     preds = workloads.config4_predicates(counts, args.batch_preds)
     outs = [cols[c].new_bv() for c, *_ in preds]
     rows = sum(int(cols[c].n_rows) for c, *_ in preds)
-    alg = 0
+    alg = alg_lines = 0
     for (c, op, lo, hi, _), o in zip(preds, outs):
         _, ctr = cols[c].scan_stats(op, lo, hi, out=o)
         alg += int(ctr[0].item())
+        alg_lines += int(ctr[4].item())
 
     def singles():
         for (c, op, lo, hi, _), o in zip(preds, outs):
@@ -771,7 +772,9 @@ def batch_main(args):
         "speedup": round(single_ms / batch_ms, 3), "solo_tiles": best[0], "grid": best[1],
         "tiles_per_grab": _grab_name(best[2]), "streams": best[3],
         "one_stream_ms": None if one_stream is None else round(one_stream, 3),
-        "alg_bytes": alg, "batch_hbm_frac": round(alg / (batch_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "alg_bytes": alg_lines, "exact_alg_bytes": alg,
+        "batch_hbm_frac": round(alg_lines / (batch_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "batch_hbm_frac_exact": round(alg / (batch_ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "single_gtuples": round(rows / (single_ms * 1e-3) / 1e9, 1),
     }
     print(json.dumps(out), flush=True)
@@ -1031,7 +1034,7 @@ def main():
             _, ctr = col.scan_stats(op, lo, hi, out=out_bv)
             torch.cuda.synchronize()
             c = ctr.cpu().numpy()
-            alg[(lay, i)] = (int(c[0]), int(c[3]))
+            alg[(lay, i)] = (int(c[0]), int(c[3]), int(c[4]))
     progress("counters done")
     tune_info = None
     if not args.no_tune:
@@ -1047,60 +1050,88 @@ def main():
 
     stream = torch.cuda.current_stream()
     n_ev = len(layouts) * (len(preds) + 1)
-    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_ev)]
 
-    def step():
+    def new_events(k):
+        return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)]
+
+    # Timed steps: per layout, one pair of events around its scans (launched back
+    # to back) and one around its lookup; the steps themselves run back to back
+    # with no host wait between them (a device left idle between steps starts the
+    # next one slower, and an event pair around every launch adds its own gaps).
+    timed_events = [new_events(2 * len(layouts)) for _ in range(max(1, args.steps))]
+    # one more step with an event pair around every launch, for the per-predicate times
+    launch_events = new_events(n_ev)
+
+    def step(ev):
+        e = 0
+        for lay in layouts:
+            col = cols[lay][1]
+            ev[e][0].record(stream)
+            for op, lo, hi, _ in preds:
+                col.scan(op, lo, hi, out=out_bv)
+            ev[e][1].record(stream)
+            ev[e + 1][0].record(stream)
+            if not args.no_lookup:
+                col.lookup(ids_t, out=out_vals)
+            ev[e + 1][1].record(stream)
+            e += 2
+
+    def step_by_launch(ev):
         e = 0
         for lay in layouts:
             col = cols[lay][1]
             for op, lo, hi, _ in preds:
-                events[e][0].record(stream)
+                ev[e][0].record(stream)
                 col.scan(op, lo, hi, out=out_bv)
-                events[e][1].record(stream)
+                ev[e][1].record(stream)
                 e += 1
-            events[e][0].record(stream)
+            ev[e][0].record(stream)
             if not args.no_lookup:
                 col.lookup(ids_t, out=out_vals)
-            events[e][1].record(stream)
+            ev[e][1].record(stream)
             e += 1
 
-    def durations():
-        torch.cuda.synchronize()
-        return [a.elapsed_time(b) for a, b in events]
-
     for _ in range(args.warmup):
-        step()
+        step(timed_events[0])
     torch.cuda.synchronize()
     progress("warmup done; timing %d steps" % args.steps)
-    acc = np.zeros(n_ev)
-    t_total = 0.0
-    for _ in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
-        t_total += time.perf_counter() - t0
-        acc += np.asarray(durations())
-    dur = acc / args.steps   # ms per launch, averaged over steps
-    ms_per_step = t_total / args.steps * 1e3
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(timed_events[k])
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    acc = np.zeros(2 * len(layouts))
+    for k in range(args.steps):
+        acc += np.asarray([a.elapsed_time(b) for a, b in timed_events[k]])
+    dur = acc / max(1, args.steps)   # ms per layout's scans and per lookup, averaged over steps
+    ms_per_step = t_total / max(1, args.steps) * 1e3
+    step_by_launch(launch_events)
+    torch.cuda.synchronize()
+    by_launch = [a.elapsed_time(b) for a, b in launch_events]
 
     res = {}
-    e = 0
-    for lay in layouts:
-        scan_ms = dur[e:e + len(preds)]
+    for li, lay in enumerate(layouts):
+        scans_ms = float(dur[2 * li])            # the layout's scans, back to back
+        lookup_ms = float(dur[2 * li + 1])
         alg_b = np.array([alg[(lay, i)][0] for i in range(len(preds))], dtype=np.float64)
         full_b = np.array([alg[(lay, i)][1] for i in range(len(preds))], dtype=np.float64)
+        line_b = np.array([alg[(lay, i)][2] for i in range(len(preds))], dtype=np.float64)
         res[lay] = {
-            "scan_gtuples": n * len(preds) / (scan_ms.sum() * 1e-3) / 1e9,
-            "scan_ms": scan_ms.tolist(),
-            "alg_gbs": alg_b.sum() / (scan_ms.sum() * 1e-3) / 1e9,
-            "alg_bytes_per_launch": float(alg_b.mean()),
+            "scan_gtuples": n * len(preds) / (scans_ms * 1e-3) / 1e9,
+            "scan_ms_avg": scans_ms / len(preds),
+            # per predicate, from the extra step with events around every launch
+            "scan_ms": by_launch[li * (len(preds) + 1):li * (len(preds) + 1) + len(preds)],
+            # algorithmic bytes at 128-byte granularity (the lines that hold them)
+            # per second: the peak-equivalent rate; and the exact bytes' rate
+            "alg_gbs": line_b.sum() / (scans_ms * 1e-3) / 1e9,
+            "alg_bytes_per_launch": float(line_b.mean()),
+            "exact_gbs": alg_b.sum() / (scans_ms * 1e-3) / 1e9,
+            "exact_bytes_per_launch": float(alg_b.mean()),
             "full_bytes_per_launch": float(full_b.mean()),
-            "lookup_ms": float(dur[e + len(preds)]),
+            "lookup_ms": lookup_ms,
             "lookup_alg_bytes_per_id": lookup_alg_bytes_per_id(cols[lay][0].info),
-            "lookup_mrows": (ids.shape[0] / (dur[e + len(preds)] * 1e-3) / 1e6) if not args.no_lookup else None,
+            "lookup_mrows": (ids.shape[0] / (lookup_ms * 1e-3) / 1e6) if not args.no_lookup else None,
         }
-        e += len(preds) + 1
 
     main_lay = "ppvbs" if "ppvbs" in res else layouts[0]
     r = res[main_lay]
@@ -1127,17 +1158,19 @@ def main():
         "traffic": traffic,
         "kernel": "%s (%s)" % ("k_scan_packed" if main_lay == "bitpacked" else "k_scan_slices", lay_name),
         "alg_bytes_per_launch": r["alg_bytes_per_launch"],
-        "avg_launch_ms": float(np.mean(r["scan_ms"])),
+        "granularity_bytes": 128,
+        # the same algorithmic bytes counted exactly (not rounded to lines)
+        "exact_alg_bytes_per_launch": r["exact_bytes_per_launch"],
+        "exact_frac": round(r["exact_gbs"] / HBM_PEAK_GBS, 4),
+        # bytes early stop saved: a scan without it reads every row's bytes up to
+        # the literal's length and the masks past them
+        "bytes_skipped_per_launch": round(r["full_bytes_per_launch"] - r["exact_bytes_per_launch"]),
+        "avg_launch_ms": r["scan_ms_avg"],
         # HBM bytes moved per second (counter traffic / launch time), and the
         # streaming probe's rate on the same bytes' shape: how close the scan's
         # actual traffic runs to what this chip streams
-        "traffic_gbs": None if traffic is None else round(traffic / (np.mean(r["scan_ms"]) * 1e-3) / 1e9, 1),
+        "traffic_gbs": None if traffic is None else round(traffic / (r["scan_ms_avg"] * 1e-3) / 1e9, 1),
         "probe_gbs": None if probe_gbs is None else round(probe_gbs, 1),
-        # the bytes a scan without early stop would read (every row's whole code,
-        # the result and any incoming mask) over the same launch time: the rate
-        # at which the column's codes are evaluated, against the same peak
-        "full_scan_gbs": round(r["full_bytes_per_launch"] / (np.mean(r["scan_ms"]) * 1e-3) / 1e9, 1),
-        "full_scan_frac": round(r["full_bytes_per_launch"] / (np.mean(r["scan_ms"]) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
     lookup_roofline = None
     if not args.no_lookup:
@@ -1181,7 +1214,9 @@ def main():
         "layouts": {lay: {
             "scan_gtuples": round(v["scan_gtuples"], 3),
             "scan_hbm_frac": round(v["alg_gbs"] / HBM_PEAK_GBS, 4),
+            "scan_hbm_frac_exact": round(v["exact_gbs"] / HBM_PEAK_GBS, 4),
             "alg_bytes_per_launch": round(v["alg_bytes_per_launch"]),
+            "exact_alg_bytes_per_launch": round(v["exact_bytes_per_launch"]),
             "full_bytes_per_launch": round(v["full_bytes_per_launch"]),
             "lookup_mrows": None if v["lookup_mrows"] is None else round(v["lookup_mrows"], 1),
             "lookup_hbm_frac": None if v["lookup_mrows"] is None else round(
@@ -1193,8 +1228,10 @@ def main():
     for lay in layouts:
         progress("%-9s scan us per predicate: %s" % (lay, " ".join("%.0f" % (1e3 * v) for v in res[lay]["scan_ms"])))
     for lay in layouts:
-        progress("%-9s scan %.1f Gtuples/s  (%.0f GB/s algorithmic, %.1f%% of 8 TB/s)  lookup %s Mrows/s" % (
+        progress("%-9s scan %.1f Gtuples/s  (%.0f GB/s algorithmic at 128 B, %.1f%% of 8 TB/s; exact bytes %.1f%%)"
+                 "  lookup %s Mrows/s" % (
             lay, res[lay]["scan_gtuples"], res[lay]["alg_gbs"], 100 * res[lay]["alg_gbs"] / HBM_PEAK_GBS,
+            100 * res[lay]["exact_gbs"] / HBM_PEAK_GBS,
             "-" if res[lay]["lookup_mrows"] is None else "%.0f" % res[lay]["lookup_mrows"]))
     if args.batch:
         # the same step's scans as one persistent launch (replayed from a HIP graph)
@@ -1210,7 +1247,8 @@ def main():
         b, best, table = autotune_batch(specs, outs, grids=[cus * 2, cus * 3, cus * 4, cus * 8],
                                         grabs=(8, 16, 32, 64, L.BATCH_ROUND_ROBIN), streams=(1,), repeats=3)
         batch_ms = time_call(lambda: b.launch(best[1], best[2], True), repeats=5)
-        single_ms = float(sum(sum(res[lay]["scan_ms"]) for lay in layouts))
+        # the timed steps' single launches, back to back
+        single_ms = float(sum(res[lay]["scan_ms_avg"] * len(preds) for lay in layouts))
         out["batch"] = {"scans": len(specs), "solo_tiles": best[0], "grid": best[1],
                         "tiles_per_grab": _grab_name(best[2]), "streams": best[3],
                         "batch_ms": round(batch_ms, 3), "single_launches_ms": round(single_ms, 3),

@@ -221,12 +221,14 @@ int bst_scan_codes(const bst_column* col, int op, uint64_t code_lo, uint32_t len
                    uint64_t code_hi, uint32_t len_hi, const uint64_t* in_mask,
                    uint64_t* out_bv, void* stream);
 /*
- * Instrumented scan: same result as bst_scan, and adds to dev_counters[0..3]
+ * Instrumented scan: same result as bst_scan, and adds to dev_counters[0..4]
  * (uint64, device): [0] algorithmic bytes (slice bytes, mask words and
  * bitvector words the early-stopping scan must touch, counted per 64-row
  * group), [1] code bytes examined summed over rows (Lemma 1 bounds each row by
  * min(l(v), l(c))), [2] 64-row groups that needed a byte beyond BS_1,
- * [3] bytes a scan without early stop would touch.
+ * [3] bytes a scan without early stop would touch, [4] the bytes of [0] at
+ * 128-byte granularity: 128 x the lines (by offset in their buffer) that hold
+ * them, each line counted once per tile and level.
  */
 int bst_scan_stats(const bst_column* col, bst_pred pred, const uint64_t* in_mask,
                    uint64_t* out_bv, uint64_t* dev_counters, void* stream);

@@ -164,7 +164,7 @@ class DeviceColumn:
 
     def scan_stats(self, op, lo, hi=None, in_mask=None, out=None, stream=None):
         out = self.new_bv() if out is None else out
-        counters = torch.zeros(4, dtype=torch.int64, device=self.device)
+        counters = torch.zeros(5, dtype=torch.int64, device=self.device)
         L.bst_scan_stats(self.h, make_pred(op, lo, hi), in_mask, out, counters, stream_handle(stream))
         return out, counters
 

@@ -98,6 +98,7 @@ __device__ __forceinline__ uint64_t lane_slice_pos(uint64_t r) {
 
 struct Stats {
     uint64_t alg = 0, rowbytes = 0, deep_groups = 0, full = 0;
+    uint64_t lines = 0;   // 128-byte lines holding the algorithmic bytes (each counted once)
 };
 
 // M_j word of 64-row group g (PP-VBS), and in `before` the j-th bytes of the
@@ -175,6 +176,7 @@ __device__ __forceinline__ void flush_stats(unsigned long long* counters, const 
         atomicAdd(counters + 1, (unsigned long long)st.rowbytes);
         atomicAdd(counters + 2, (unsigned long long)st.deep_groups);
         atomicAdd(counters + 3, (unsigned long long)st.full);
+        atomicAdd(counters + 4, (unsigned long long)(st.lines * 128));
     }
 }
 

@@ -18,6 +18,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_packed(const DevCol c, const Pa
         Stats st;
         st.alg = alg;
         st.full = alg;
+        st.lines = alg / 128;   // whole words of whole tiles: every byte's line is read in full
         flush_stats(counters, st, lane);
     }
 }

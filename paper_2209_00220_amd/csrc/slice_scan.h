@@ -123,6 +123,32 @@ __device__ __forceinline__ uint32_t groups_with(uint32_t v) {
     return (uint32_t)__builtin_popcountll((b | (b >> 1)) & 0x5555555555555555ull);
 }
 
+// 128-byte lines holding the M_j words of the groups in which v is non-zero in
+// either lane (a tile's 32 words fill two lines: lanes 0-31 and 32-63).
+__device__ __forceinline__ uint32_t mask_lines(uint32_t v) {
+    const uint64_t b = ballot(v != 0);
+    return ((uint32_t)b != 0u ? 1u : 0u) + ((uint32_t)(b >> 32) != 0u ? 1u : 0u);
+}
+
+// 128-byte lines of a slice that the lanes' byte spans [first, first + len)
+// touch, each line once: spans of increasing lanes are disjoint and increasing,
+// so a line two spans share is the last of one and the first of the next
+// non-empty one.  Uniform; for the instrumented build only.
+__device__ inline uint32_t span_lines(uint64_t first, uint32_t len) {
+    uint32_t lines = 0;
+    uint64_t prev = ~0ull;
+    for (int i = 0; i < 64; ++i) {
+        const uint32_t l = (uint32_t)__builtin_amdgcn_readlane((int)len, i);
+        if (!l) continue;
+        const uint64_t f = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(first >> 32), i) << 32) |
+                           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)first, i);
+        const uint64_t a = f >> 7, b = (f + l - 1) >> 7;
+        lines += (uint32_t)(b - a + 1) - (a == prev ? 1u : 0u);
+        prev = b;
+    }
+    return lines;
+}
+
 // True in both lanes of a lane pair when v is non-zero in either.
 __device__ __forceinline__ bool pair_any(uint32_t v, uint32_t lane) {
     const uint64_t b = ballot(v != 0);
@@ -319,13 +345,17 @@ struct SliceScan {
         return load_tile<kNeedM2, kNeedDir, HAS_IN>(c, in_mask, t, lane, valid);
     }
 
-    // Lemma-1 counters of a level's pending rows (instrumented build only).
-    __device__ static void count_level(Stats& st, uint32_t j, uint32_t pend, uint32_t mj, uint32_t lane) {
+    // Lemma-1 counters of a level's pending rows (instrumented build only);
+    // first: the offset in BS_j of the lane's first byte there.
+    __device__ static void count_level(Stats& st, uint32_t j, uint32_t pend, uint32_t mj, uint32_t lane,
+                                       uint64_t first) {
         const bool g = pair_any(pend, lane);
         if (j == 2) st.deep_groups += groups_with(pend);
         st.rowbytes += wave_total(__builtin_popcount(pend));
         // the group's bytes of BS_j: PP-VBS the M_j word's bits, ByteSlice all 64
-        st.alg += wave_total(g ? (DENSE ? 32u : (uint32_t)__builtin_popcount(mj)) : 0u);
+        const uint32_t len = g ? (DENSE ? 32u : (uint32_t)__builtin_popcount(mj)) : 0u;
+        st.alg += wave_total(len);
+        st.lines += span_lines(first, len);
     }
 
     // Byte 1 and the presence of byte 2 for tile t; then, if rows are still
@@ -358,10 +388,18 @@ struct SliceScan {
         if (MODE == kModeBetween) phi = ~neh & act;
         if (COUNT) {
             st.alg += kTileRows + 256 + (HAS_IN ? 256 : 0);
+            st.lines += (kTileRows + 256 + (HAS_IN ? 256 : 0)) / 128;
             st.full += full_read_bytes<DENSE>(c, lit, t, HAS_IN);
             st.rowbytes += wave_total(__builtin_popcount(act));
-            // M_2 words read: the groups with rows equal on byte 1
-            if (!DENSE && K >= 2) st.alg += 8ull * groups_with(plo | phi);
+            // M_2 words read: the groups with rows equal on byte 1, except rows
+            // equal to a one-byte '<' or lower-BETWEEN literal, which are not
+            // below it whatever follows (this build takes lengths at run time)
+            const bool lo_m2 = !((MODE == kModeLT || MODE == kModeBetween) && lit.llo == 1);
+            const uint32_t tied1 = (lo_m2 ? plo : 0u) | phi;
+            if (!DENSE && K >= 2) {
+                st.alg += 8ull * groups_with(tied1);
+                st.lines += mask_lines(tied1);
+            }
         }
         // byte 2's presence settles the rows equal on byte 1 that end there
         const uint32_t klo = SHORT < 0 ? (1 < lit.llo ? ~0u : 0u) : (kLoShort ? 0u : ~0u);
@@ -377,8 +415,8 @@ struct SliceScan {
         if constexpr (kByte1Only) return;
         const uint32_t pend = plo | phi;
         if (!wave_any(pend != 0)) return;
-        if (COUNT) count_level(st, 2, pend, td.m2, lane);
         if constexpr (DENSE) {
+            if (COUNT) count_level(st, 2, pend, td.m2, lane, t * kTileRows + lane * 32);
             // the pending lanes' 32 bytes of BS_2 (contiguous per lane), held in the
             // same registers as BS_1's
             const auto r2 = buffer_rsrc(c.bs[2] + t * kTileRows, kTileRows);
@@ -388,6 +426,7 @@ struct SliceScan {
             const uint32_t incl = wave_incl_sum((uint32_t)__builtin_popcount(td.m2));
             const uint32_t runlen = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
             const uint32_t run0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)td.dir2);
+            if (COUNT) count_level(st, 2, pend, td.m2, lane, (uint64_t)run0 + incl - __builtin_popcount(td.m2));
             const uint32_t cnt = (uint32_t)__builtin_popcount(pend);
             if (wave_any(cnt > lit.gather)) {
                 // a lane with more pending rows than it gathers: the whole tile's
@@ -441,6 +480,7 @@ struct SliceScan {
             if (COUNT && !DENSE && K > 2) {
                 const uint32_t tied = (s.plo & elo) | (MODE == kModeBetween ? (s.phi & ehi) : 0u);
                 st.alg += 8ull * groups_with(tied);
+                st.lines += mask_lines(tied);
             }
             apply_level<MODE>(s.out, s.plo, s.phi, rlo, elo, rhi, ehi, m, 2 < lit.llo ? ~0u : 0u,
                               2 < lit.lhi ? ~0u : 0u);
@@ -482,6 +522,7 @@ struct SliceScan {
         if (COUNT && j < K) {
             const uint32_t tied = (s.plo & elo) | (MODE == kModeBetween ? (s.phi & ehi) : 0u);
             st.alg += 8ull * groups_with(tied);
+            st.lines += mask_lines(tied);
         }
         apply_level<MODE>(s.out, s.plo, s.phi, rlo, elo, rhi, ehi, m, j < lit.llo ? ~0u : 0u,
                           j < lit.lhi ? ~0u : 0u);
@@ -500,7 +541,7 @@ struct SliceScan {
             const uint32_t cl = lit_byte(lit.lo, j), ch = lit_byte(lit.hi, j);
             uint32_t rlo = 0, elo = 0, rhi = 0, ehi = 0, m;
             if constexpr (DENSE) {
-                if (COUNT) count_level(st, j, pend, 0u, lane);
+                if (COUNT) count_level(st, j, pend, 0u, lane, t * kTileRows + lane * 32);
                 uint32_t x[8];
                 load_lane_bytes<16>(buffer_rsrc(c.bs[j] + t * kTileRows, kTileRows), pend ? lane * 32 : kOutOfRange, x);
                 lane_masks<MODE>(x, cl, ch, rlo, elo, rhi, ehi);
@@ -508,11 +549,11 @@ struct SliceScan {
             } else {
                 const uint32_t mj = load_mask_dword(c, j, t, lane * 4);
                 const uint32_t run0 = c.dir[j][(t * kTileRows) >> c.dir_shift];
-                if (COUNT) count_level(st, j, pend, mj, lane);
                 const uint32_t pc = (uint32_t)__builtin_popcount(mj);
                 const uint32_t incl = wave_incl_sum(pc);
                 const uint32_t runlen = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
                 const uint32_t excl = incl - pc;
+                if (COUNT) count_level(st, j, pend, mj, lane, (uint64_t)run0 + excl);
                 if (wave_any((uint32_t)__builtin_popcount(pend) > lit.gather)) {
                     settle_staged(c, lit, t, j, run0, runlen, excl, mj, lane, s, lds, st);
                     continue;
@@ -536,6 +577,7 @@ struct SliceScan {
             if (COUNT && !DENSE && j < K) {
                 const uint32_t tied = (s.plo & elo) | (MODE == kModeBetween ? (s.phi & ehi) : 0u);
                 st.alg += 8ull * groups_with(tied);
+                st.lines += mask_lines(tied);
             }
             apply_level<MODE>(s.out, s.plo, s.phi, rlo, elo, rhi, ehi, m, j < lit.llo ? ~0u : 0u,
                               j < lit.lhi ? ~0u : 0u);

@@ -192,12 +192,21 @@ def test_early_stop_counters_lemma1():
                 assert int(ctr[1]) == int(m.sum()), (k, op)
                 assert int(m.sum()) <= int(np.minimum(Lc[rank], Lc[k]).sum())
                 assert 0 < int(ctr[0]) <= int(ctr[3])
+                # the same bytes at 128-byte granularity: whole lines, at least the
+                # bytes themselves, at most the lines an exhaustive read of each
+                # tile's runs touches (its bytes plus one partial line per run)
+                tiles = (n + 2047) // 2048
+                assert int(ctr[4]) % 128 == 0 and int(ctr[0]) <= int(ctr[4])
+                assert int(ctr[4]) <= int(ctr[3]) + 128 * tiles * (int(Lc.max()) - 1), (k, op)
+                if op == "lt" and Lc[k] == 1:   # settled by byte 1 alone: BS_1 and the result
+                    assert int(ctr[4]) == int(ctr[0]) == tiles * (2048 + 256)
                 assert np.array_equal(_bv(bv), scan_values_bv(x, op, int(A[k])))
         # ByteSlice: fixed 2-byte codes, counters bounded by the full read
         bvb, cb = cols["byteslice"][1].scan_stats("lt", int(A[len(A) // 3]))
         torch.cuda.synchronize()
         cb = cb.cpu().numpy()
         assert 0 < int(cb[0]) <= int(cb[3])
+        assert int(cb[4]) % 128 == 0 and int(cb[0]) <= int(cb[4]) <= int(cb[3])
     finally:
         close_columns(cols)
 
