@@ -1109,6 +1109,27 @@ def main():
     torch.cuda.synchronize()
     by_launch = [a.elapsed_time(b) for a, b in launch_events]
 
+    # Outside the timed steps: the lookups with the same IDs in ascending order,
+    # and each layout's scans cold -- one launch per predicate right after a
+    # 1 GiB write, which evicts the last-level cache (256 MB) -- each launch
+    # between its own pair of events.
+    sorted_ids_t = u32_from_numpy(np.sort(ids))
+    flush_buf = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    sorted_ms, cold_ms = {}, {}
+    for lay in layouts:
+        col = cols[lay][1]
+        sorted_ms[lay] = None if args.no_lookup else _ms_events(lambda: col.lookup(sorted_ids_t, out=out_vals))
+        cold_ms[lay] = 0.0
+        for op, lo, hi, _ in preds:
+            flush_buf.fill_(1)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            col.scan(op, lo, hi, out=out_bv)
+            b.record(stream)
+            b.synchronize()
+            cold_ms[lay] += a.elapsed_time(b)
+    del flush_buf, sorted_ids_t
+
     res = {}
     for li, lay in enumerate(layouts):
         scans_ms = float(dur[2 * li])            # the layout's scans, back to back
@@ -1131,6 +1152,8 @@ def main():
             "lookup_ms": lookup_ms,
             "lookup_alg_bytes_per_id": lookup_alg_bytes_per_id(cols[lay][0].info),
             "lookup_mrows": (ids.shape[0] / (lookup_ms * 1e-3) / 1e6) if not args.no_lookup else None,
+            "lookup_sorted_mrows": None if sorted_ms[lay] is None else ids.shape[0] / (sorted_ms[lay] * 1e-3) / 1e6,
+            "cold_scan_gtuples": n * len(preds) / (cold_ms[lay] * 1e-3) / 1e9,
         }
 
     main_lay = "ppvbs" if "ppvbs" in res else layouts[0]
@@ -1219,6 +1242,8 @@ def main():
             "exact_alg_bytes_per_launch": round(v["exact_bytes_per_launch"]),
             "full_bytes_per_launch": round(v["full_bytes_per_launch"]),
             "lookup_mrows": None if v["lookup_mrows"] is None else round(v["lookup_mrows"], 1),
+            "lookup_sorted_ids_mrows": None if v["lookup_sorted_mrows"] is None else round(v["lookup_sorted_mrows"], 1),
+            "cold_scan_gtuples": round(v["cold_scan_gtuples"], 3),
             "lookup_hbm_frac": None if v["lookup_mrows"] is None else round(
                 v["lookup_alg_bytes_per_id"] * ids.shape[0] / (v["lookup_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         } for lay, v in res.items()},
@@ -1233,6 +1258,10 @@ def main():
             lay, res[lay]["scan_gtuples"], res[lay]["alg_gbs"], 100 * res[lay]["alg_gbs"] / HBM_PEAK_GBS,
             100 * res[lay]["exact_gbs"] / HBM_PEAK_GBS,
             "-" if res[lay]["lookup_mrows"] is None else "%.0f" % res[lay]["lookup_mrows"]))
+    for lay in layouts:
+        progress("%-9s cold scans %.1f Gtuples/s; lookup of the IDs sorted %s Mrows/s" % (
+            lay, res[lay]["cold_scan_gtuples"],
+            "-" if res[lay]["lookup_sorted_mrows"] is None else "%.0f" % res[lay]["lookup_sorted_mrows"]))
     if args.batch:
         # the same step's scans as one persistent launch (replayed from a HIP graph)
         from paper_2209_00220_amd import _lib as L
