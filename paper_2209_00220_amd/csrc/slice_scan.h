@@ -345,6 +345,14 @@ struct SliceScan {
         return load_tile<kNeedM2, kNeedDir, HAS_IN>(c, in_mask, t, lane, valid);
     }
 
+    // Rows equal to the literals over bytes 1..j whose M_{j+1} bit the
+    // algorithm needs (instrumented build only): none of those equal to a whole
+    // '<' or lower-BETWEEN literal, which are not below it whatever follows.
+    __device__ static uint32_t tied_next(const ScanLit& lit, uint32_t j, uint32_t lo_eq, uint32_t hi_eq) {
+        const bool lo_done = (MODE == kModeLT || MODE == kModeBetween) && j >= lit.llo;
+        return (lo_done ? 0u : lo_eq) | (MODE == kModeBetween ? hi_eq : 0u);
+    }
+
     // Lemma-1 counters of a level's pending rows (instrumented build only);
     // first: the offset in BS_j of the lane's first byte there.
     __device__ static void count_level(Stats& st, uint32_t j, uint32_t pend, uint32_t mj, uint32_t lane,
@@ -391,11 +399,8 @@ struct SliceScan {
             st.lines += (kTileRows + 256 + (HAS_IN ? 256 : 0)) / 128;
             st.full += full_read_bytes<DENSE>(c, lit, t, HAS_IN);
             st.rowbytes += wave_total(__builtin_popcount(act));
-            // M_2 words read: the groups with rows equal on byte 1, except rows
-            // equal to a one-byte '<' or lower-BETWEEN literal, which are not
-            // below it whatever follows (this build takes lengths at run time)
-            const bool lo_m2 = !((MODE == kModeLT || MODE == kModeBetween) && lit.llo == 1);
-            const uint32_t tied1 = (lo_m2 ? plo : 0u) | phi;
+            // M_2 words read: the groups with rows equal on byte 1 that need them
+            const uint32_t tied1 = tied_next(lit, 1, plo, phi);
             if (!DENSE && K >= 2) {
                 st.alg += 8ull * groups_with(tied1);
                 st.lines += mask_lines(tied1);
@@ -478,7 +483,7 @@ struct SliceScan {
                 m = s.mnext;
             }
             if (COUNT && !DENSE && K > 2) {
-                const uint32_t tied = (s.plo & elo) | (MODE == kModeBetween ? (s.phi & ehi) : 0u);
+                const uint32_t tied = tied_next(lit, 2, s.plo & elo, s.phi & ehi);
                 st.alg += 8ull * groups_with(tied);
                 st.lines += mask_lines(tied);
             }
@@ -520,7 +525,7 @@ struct SliceScan {
         const uint32_t pend = s.plo | s.phi;
         const uint32_t m = j < K ? load_mask_dword(c, j + 1, t, pend ? lane * 4 : kOutOfRange) : 0u;
         if (COUNT && j < K) {
-            const uint32_t tied = (s.plo & elo) | (MODE == kModeBetween ? (s.phi & ehi) : 0u);
+            const uint32_t tied = tied_next(lit, j, s.plo & elo, s.phi & ehi);
             st.alg += 8ull * groups_with(tied);
             st.lines += mask_lines(tied);
         }
@@ -575,7 +580,7 @@ struct SliceScan {
                 });
             }
             if (COUNT && !DENSE && j < K) {
-                const uint32_t tied = (s.plo & elo) | (MODE == kModeBetween ? (s.phi & ehi) : 0u);
+                const uint32_t tied = tied_next(lit, j, s.plo & elo, s.phi & ehi);
                 st.alg += 8ull * groups_with(tied);
                 st.lines += mask_lines(tied);
             }

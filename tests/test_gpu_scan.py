@@ -211,6 +211,68 @@ def test_early_stop_counters_lemma1():
         close_columns(cols)
 
 
+def _expected_touch(P, Lr, K, lit, l, op):
+    """Counters 0 and 4 of an instrumented PP-VBS scan with one literal (code
+    `lit` of l bytes), from their definitions on the rows' padded codes P and
+    lengths Lr: per 2048-row tile, BS_1 and the result words; at each byte j of
+    the literal, the BS_j bytes of every 64-row group holding a row that is
+    equal to the literal over bytes 1..j-1 and has a j-th byte; after byte j,
+    the M_{j+1} words of the groups holding rows equal over bytes 1..j, unless
+    j is the last byte of a '<' literal (such rows are not below it).  Counter 0
+    sums the bytes, counter 4 is 128 x the distinct 128-byte lines (by offset in
+    the slice) that hold them, per tile and level."""
+    n = P.shape[0]
+    tiles = (n + 2047) // 2048
+    exact, lines = tiles * (2048 + 256), tiles * 18
+    rows = np.arange(n, dtype=np.int64)
+    group, tile = rows // 64, rows // 2048
+    eq = np.ones(n, dtype=bool)
+    for j in range(1, l + 1):
+        byte = (P >> np.uint64(8 * (K - j))) & np.uint64(0xFF)
+        has = Lr >= j
+        if j >= 2:
+            pend_groups = np.unique(group[eq & has])
+            touched = np.isin(group, pend_groups) & has
+            pos = np.cumsum(has) - 1                      # position in BS_j
+            exact += int(touched.sum())
+            lines += np.unique(tile[touched] * (1 << 40) + pos[touched] // 128).shape[0]
+        eq &= has & (byte == np.uint64((lit >> (8 * (l - j))) & 0xFF))
+        if j < K and not (op == "lt" and j == l):
+            tied_groups = np.unique(group[eq])
+            exact += 8 * tied_groups.shape[0]
+            lines += np.unique(tied_groups // 16).shape[0]
+    return exact, 128 * lines
+
+
+def test_touch_counters_exact():
+    """The instrumented scan's algorithmic bytes, exact and at 128-byte
+    granularity, equal their definitions computed from the oracle's codes, for
+    literals of one, two and three bytes, over a column with a ragged tail."""
+    n = 200_001
+    x = datagen.zipf_column(n, 16, 1.0, seed=23, mapping=datagen.SORTED)
+    A, Q, rank = build_dictionary(x)
+    C, Lc = ppe_numerical(Q)
+    K = int(Lc.max())
+    assert K >= 3
+    P = padded(C[rank], Lc[rank], K)
+    Lr = Lc[rank]
+    cols = device_columns(x, 16, layouts=("ppvbs",))
+    try:
+        col = cols["ppvbs"][1]
+        picks = [int(np.flatnonzero(Lc == L)[i]) for L in (1, 2, 3) for i in (0, 5)]
+        for k in picks:
+            for op in ("lt", "gt", "eq"):
+                if (op == "lt" and k == 0) or (op == "gt" and k == len(A) - 1):
+                    continue
+                _, ctr = col.scan_stats(op, int(A[k]))
+                torch.cuda.synchronize()
+                ctr = ctr.cpu().numpy()
+                want = _expected_touch(P, Lr, K, int(C[k]), int(Lc[k]), op)
+                assert (int(ctr[0]), int(ctr[4])) == want, (k, int(Lc[k]), op)
+    finally:
+        close_columns(cols)
+
+
 def test_repeatable():
     n = 500_000
     x = datagen.zipf_column(n, 20, 1.0, seed=77)
