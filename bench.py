@@ -321,6 +321,15 @@ def summarize_counters(fetch_dir: str, write_dir: str, cmds, out_path: str, pred
         return rows
 
     fr, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    # the counter run's own benchmark line (its stdout, beside the counter folder):
+    # the in-kernel byte counters of each predicate
+    counted = {}
+    bench_out = fetch_dir.rstrip("/") + ".out"
+    if os.path.exists(bench_out):
+        for ln in open(bench_out):
+            if ln.startswith("{"):
+                lay_res = json.loads(ln).get("layouts", {})
+                counted = {lay: v.get("counters_by_predicate") for lay, v in lay_res.items()}
     copy_f = [r for r in fr if "copyBuffer" in r["Kernel_Name"]][0]
     copy_w = [r for r in wr if "copyBuffer" in r["Kernel_Name"]][0]
     gib = float(1 << 30)
@@ -329,17 +338,22 @@ def summarize_counters(fetch_dir: str, write_dir: str, cmds, out_path: str, pred
     fs, ws = _step_launches(fr, 1, len(preds), layouts), _step_launches(wr, 1, len(preds), layouts)
     order = _step_layout_order(len(preds), layouts)
     assert len(fs) == len(ws) == len(order), (len(fs), len(ws), len(order))
-    lines = ["HBM traffic per launch of the benchmark step (500M-row column, 20-bit Zipf(1.0)), from",
+    lines = (["HBM traffic per launch of the benchmark step (500M-row column, 20-bit Zipf(1.0)), from",
              "two rocprofv3 counter runs of a one-step benchmark; kernel_hash names the scan kernel",
              "sources these counters were taken on (bench.py reports roofline.traffic only when it",
              "matches the current sources).",
              "",
-             "commands (repo root; TMPDIR=/tmp):"] + ["  " + c for c in cmds] + [
+             "commands (repo root; TMPDIR=/tmp; the first run's stdout goes to gpurun_out/pmc_fetch.out):"] +
+             ["  " + c for c in cmds] + [
              "  python3 bench.py --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write --out profiles/scan_lookup_500M_traffic.txt",
+             "",
+             "Per scan, beside the measured traffic, the kernel's own byte counters (bst_scan_stats, MB):",
+             "alg128 = algorithmic bytes at 128-byte granularity, exact = the same bytes exactly,",
+             "no-stop = what a scan without early stop would read, skipped = no-stop - exact.",
              "",
              "calibration: the 1 GiB device-to-device copy reads FETCH_SIZE = %.1f KiB and writes WRITE_SIZE = %.1f KiB;"
              % (float(copy_f["Counter_Value"]), float(copy_w["Counter_Value"])),
-             "fetch is scaled x%.3f and write x%.3f below." % (f_scale, w_scale), ""]
+             "fetch is scaled x%.3f and write x%.3f below." % (f_scale, w_scale), ""])
     per_lay = {}
     for (lay, i), a, b in zip(order, fs, ws):
         assert a["Kernel_Name"] == b["Kernel_Name"]
@@ -348,16 +362,27 @@ def summarize_counters(fetch_dir: str, write_dir: str, cmds, out_path: str, pred
         per_lay.setdefault(lay, []).append((i, _short(a["Kernel_Name"]), fb, wb))
     for lay in layouts:
         lines.append("%s launches (fetch and write MB per launch, scaled):" % lay)
-        scans = []
+        scans, ctrs = [], []
         for i, name, fb, wb in per_lay[lay]:
             if i == "lookup":
                 lines.append("  %-8s %-16s %-45s fetch %8.1f  write %6.1f" % ("lookup", "5M ids", name, fb / 1e6, wb / 1e6))
                 continue
             op, lo, hi, _ = preds[i]
             lit = "%d..%d" % (lo, hi) if hi is not None else "%d" % lo
-            lines.append("  %-8s %-16s %-45s fetch %8.1f  write %6.1f" % (op, lit, name, fb / 1e6, wb / 1e6))
+            row = "  %-8s %-16s %-45s fetch %8.1f  write %6.1f" % (op, lit, name, fb / 1e6, wb / 1e6)
+            c = (counted.get(lay) or [None] * len(preds))[i]
+            if c is not None:
+                exact, full, l128 = c
+                row += "   alg128 %7.1f  exact %7.1f  no-stop %7.1f  skipped %7.1f" % (
+                    l128 / 1e6, exact / 1e6, full / 1e6, (full - exact) / 1e6)
+                ctrs.append(c)
+            lines.append(row)
             scans.append(fb + wb)
         lines.append("  average HBM bytes per scan launch: %.0f" % np.mean(scans))
+        if ctrs:
+            m = np.mean(np.array(ctrs, dtype=np.float64), axis=0)
+            lines.append("  average counted MB per scan launch: alg128 %.1f, exact %.1f, no-stop %.1f, skipped %.1f"
+                         % (m[2] / 1e6, m[0] / 1e6, m[1] / 1e6, (m[1] - m[0]) / 1e6))
         lines.append("")
     pp = [fb + wb for i, _, fb, wb in per_lay.get("ppvbs", []) if i != "lookup"]
     lk = [fb + wb for i, _, fb, wb in per_lay.get("ppvbs", []) if i == "lookup"]
@@ -1241,6 +1266,9 @@ def main():
             "alg_bytes_per_launch": round(v["alg_bytes_per_launch"]),
             "exact_alg_bytes_per_launch": round(v["exact_bytes_per_launch"]),
             "full_bytes_per_launch": round(v["full_bytes_per_launch"]),
+            # per predicate, from the instrumented scans: [exact algorithmic bytes,
+            # bytes without early stop, algorithmic bytes at 128-byte granularity]
+            "counters_by_predicate": [list(alg[(lay, i)]) for i in range(len(preds))],
             "lookup_mrows": None if v["lookup_mrows"] is None else round(v["lookup_mrows"], 1),
             "lookup_sorted_ids_mrows": None if v["lookup_sorted_mrows"] is None else round(v["lookup_sorted_mrows"], 1),
             "cold_scan_gtuples": round(v["cold_scan_gtuples"], 3),
