@@ -967,8 +967,8 @@ def main():
     ap.add_argument("--batch-preds", type=int, default=256)
     ap.add_argument("--batch-streams", type=lambda v: tuple(int(x) for x in v.split(",")), default=(1, 2, 4),
                     help="stream counts the batch autotuner tries (comma-separated, each 1..4)")
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--rows", type=int, default=500_000_000)
     ap.add_argument("--cpu-sample", type=int, default=3_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -277,7 +277,6 @@ struct TileState {
     uint32_t pend;                // PP-VBS: the rows whose bytes are in flight (the lowest
                                   // kGatherSlots set bits of the lane, in ascending order)
     uint32_t b[kGatherSlots];     // their bytes
-    uint32_t mnext;               // PP-VBS: the lane's M_3 dword (lanes with pending rows)
     uint32_t d[8];                // ByteSlice: the lane's 32 bytes of BS_2 (lanes with pending rows)
     uint32_t inflight;            // uniform: level-2 bytes are in flight
 };
@@ -451,11 +450,6 @@ struct SliceScan {
                 rem ^= beta;
             });
             s.pend = pend;
-            // M_3 for the rows that tie on byte 2 (only lanes with pending rows read
-            // it); a '<' literal of at most two bytes never consults it: a row
-            // equal to it over two bytes is not below it, with or without a third
-            const bool need_m3 = K >= 3 && (MODE != kModeLT || lit.llo > 2);
-            s.mnext = need_m3 ? load_mask_dword(c, 3, t, pend ? lane * 4 : kOutOfRange) : 0u;
             s.inflight = 1;
         }
     }
@@ -480,7 +474,13 @@ struct SliceScan {
                     row_masks<MODE>(s.b[k], beta, cl, ch, rlo, elo, rhi, ehi);
                     rem ^= beta;
                 });
-                m = s.mnext;
+                // M_3 for the rows equal over two bytes, read once they are known
+                // (by the lanes holding them; few tiles have any).  A '<' literal
+                // of at most two bytes never consults it: a row equal to it over
+                // two bytes is not below it, with or without a third.
+                const bool need_m3 = K >= 3 && (MODE != kModeLT || lit.llo > 2);
+                const uint32_t tied = (s.plo & elo) | (MODE == kModeBetween ? (s.phi & ehi) : 0u);
+                m = need_m3 && wave_any(tied != 0) ? load_mask_dword(c, 3, t, tied ? lane * 4 : kOutOfRange) : 0u;
             }
             if (COUNT && !DENSE && K > 2) {
                 const uint32_t tied = tied_next(lit, 2, s.plo & elo, s.phi & ehi);
