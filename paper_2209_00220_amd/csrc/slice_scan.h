@@ -278,7 +278,7 @@ struct TileState {
                                   // kGatherSlots set bits of the lane, in ascending order)
     uint32_t b[kGatherSlots];     // their bytes
     uint32_t d[8];                // ByteSlice: the lane's 32 bytes of BS_2 (lanes with pending rows)
-    uint32_t inflight;            // uniform: level-2 bytes are in flight
+    uint32_t inflight;            // uniform: level-2 bytes are in flight (PP-VBS: the gather slots used)
 };
 
 // Bytes an exhaustive (no early stop) scan of this tile would touch.
@@ -441,16 +441,22 @@ struct SliceScan {
             }
             const auto r2 = buffer_rsrc(c.bs[2] + run0, runlen);
             const uint32_t excl = incl - (uint32_t)__builtin_popcount(td.m2);
+            // as many gather slots as the lane with the most pending rows needs
+            // (most tiles have a row or two pending in all)
+            uint32_t used = 1;
+            Unroll<1, kGatherSlots>::run([&](auto sc) { used += wave_any(cnt > (uint32_t)decltype(sc)::value) ? 1u : 0u; });
             uint32_t rem = pend;
             Unroll<0, kGatherSlots>::run([&](auto sc) {
                 constexpr int k = decltype(sc)::value;
-                const uint32_t beta = rem & (0u - rem);
-                const uint32_t off = beta ? excl + (uint32_t)__builtin_popcount(td.m2 & (beta - 1u)) : kOutOfRange;
-                s.b[k] = __builtin_amdgcn_raw_buffer_load_b8(r2, (int)off, 0, 0);
-                rem ^= beta;
+                if ((uint32_t)k < used) {
+                    const uint32_t beta = rem & (0u - rem);
+                    const uint32_t off = beta ? excl + (uint32_t)__builtin_popcount(td.m2 & (beta - 1u)) : kOutOfRange;
+                    s.b[k] = __builtin_amdgcn_raw_buffer_load_b8(r2, (int)off, 0, 0);
+                    rem ^= beta;
+                }
             });
             s.pend = pend;
-            s.inflight = 1;
+            s.inflight = used;
         }
     }
 
@@ -468,11 +474,14 @@ struct SliceScan {
                 m = K > 2 ? ~0u : 0u;
             } else {
                 uint32_t rem = s.pend;
+                const uint32_t used = (uint32_t)__builtin_amdgcn_readfirstlane((int)s.inflight);
                 Unroll<0, kGatherSlots>::run([&](auto sc) {
                     constexpr int k = decltype(sc)::value;
-                    const uint32_t beta = rem & (0u - rem);
-                    row_masks<MODE>(s.b[k], beta, cl, ch, rlo, elo, rhi, ehi);
-                    rem ^= beta;
+                    if ((uint32_t)k < used) {
+                        const uint32_t beta = rem & (0u - rem);
+                        row_masks<MODE>(s.b[k], beta, cl, ch, rlo, elo, rhi, ehi);
+                        rem ^= beta;
+                    }
                 });
                 // M_3 for the rows equal over two bytes, read once they are known
                 // (by the lanes holding them; few tiles have any).  A '<' literal
