@@ -163,18 +163,21 @@ static int build_dict(const uint32_t* x, uint64_t n, uint32_t T, Dict& d) {
         std::vector<uint32_t>().swap(uv[b]);
         std::vector<uint64_t>().swap(uc[b]);
     }
-    // ranks: a directory over the top 24 bits narrows each search to the entries
-    // that share them (first[p] = entries below p << 8; nd < 2^32), so it stays
-    // in a cache line or two instead of walking the whole sorted array
+    // ranks: a directory over the top bits (about log2 of the distinct count, at
+    // most 24) narrows each search to the entries that share them (first[p] =
+    // entries below p << shift; nd < 2^32), so it stays in a cache line or two
+    // instead of walking the whole sorted array
     const uint32_t* A = d.A.data();
     const uint64_t nd = d.A.size();
-    constexpr int kDirShift = 8;
-    std::vector<uint32_t> first((1u << (32 - kDirShift)) + 1, (uint32_t)nd);
-    for (uint64_t k = nd; k-- > 0;) first[A[k] >> kDirShift] = (uint32_t)k;
+    int bits = 8;
+    while (bits < 24 && (1ull << bits) < nd) ++bits;
+    const int shift = 32 - bits;
+    std::vector<uint32_t> first((1u << bits) + 1, (uint32_t)nd);
+    for (uint64_t k = nd; k-- > 0;) first[A[k] >> shift] = (uint32_t)k;
     for (uint64_t p = first.size() - 1; p-- > 0;) first[p] = std::min(first[p], first[p + 1]);
     parallel_chunks(n, T, 1 << 16, [&](uint64_t lo, uint64_t hi, uint32_t) {
         for (uint64_t i = lo; i < hi; ++i) {
-            const uint32_t p = x[i] >> kDirShift;
+            const uint32_t p = x[i] >> shift;
             d.rank[i] = (uint32_t)(std::lower_bound(A + first[p], A + first[p + 1], x[i]) - A);
         }
     });
