@@ -274,7 +274,7 @@ int bst_lookup_bv(const bst_column* col, const uint64_t* bv, uint32_t* out_value
  * bst_lookup_bv without caller-provided device memory, for callers that cannot
  * allocate (code under stream capture, tight serving loops, hosts that forbid
  * allocation): the compaction workspace and the row-ID staging live in a device
- * array the library holds per GPU (12.6 MB, reserved on that GPU until the
+ * array the library holds per GPU (8.4 MB, reserved on that GPU until the
  * process ends).  The caller passes only inputs and outputs, as for
  * bst_lookup_bv.  Limits: columns of at most bst_lookup_bv_static_max_rows()
  * rows (2^29) and cap at most bst_lookup_bv_static_max_ids() (2^21); larger

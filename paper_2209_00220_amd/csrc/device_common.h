@@ -71,6 +71,19 @@ struct Unroll<N, N> {
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Inclusive prefix sum over the wave's lanes: DPP row shifts within each
+// 16-lane row, then row broadcasts across rows (lanes without a source add 0).
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
+    constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowShr + 1, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowShr + 2, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowShr + 4, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowShr + 8, 0xf, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowBcast15, 0xa, 0xf, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowBcast31, 0xc, 0xf, false);
+    return v;
+}
+
 // byte j (1-based) of a literal padded to BST_KMAX bytes
 __device__ __forceinline__ uint32_t lit_byte(uint64_t lit6, uint32_t j) {
     return (uint32_t)(lit6 >> (8 * (BST_KMAX - j))) & 0xffu;

@@ -98,19 +98,6 @@ __device__ __forceinline__ void swar_lane(const uint32_t (&x)[8], ByteLit lo, By
 }
 
 // ------------------------------------------------------------ wave helpers
-// Inclusive prefix sum over the wave's lanes: DPP row shifts within each
-// 16-lane row, then row broadcasts across rows (lanes without a source add 0).
-__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
-    constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowShr + 1, 0xf, 0xf, false);
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowShr + 2, 0xf, 0xf, false);
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowShr + 4, 0xf, 0xf, false);
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowShr + 8, 0xf, 0xf, false);
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowBcast15, 0xa, 0xf, false);
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kRowBcast31, 0xc, 0xf, false);
-    return v;
-}
-
 __device__ __forceinline__ uint32_t wave_total(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_sum(v), 63);
 }
