@@ -115,6 +115,32 @@ def test_compact_and_lookup_bv(n, density):
         close_columns(cols)
 
 
+@pytest.mark.parametrize("n,density", [
+    (2048 * 64, 0.3),            # exactly one chunk of 64 tiles
+    (2048 * 64 + 1, 0.3),        # a second chunk holding one row (odd word count: a half quad at the end)
+    (2048 * 64 * 3 - 5, 0.02),   # ragged last chunk and tile
+    (2048 * 64 * 2 + 134, 0.97), # nearly every row, odd word count
+    (97, 0.5),                   # one partial tile
+])
+def test_compact_and_popcount_ignore_tail_bits(n, density):
+    """Compaction and popcount of bitvectors whose words past row n - 1 hold
+    set bits: only rows < n count, at chunk and quad boundaries."""
+    from paper_2209_00220_amd.column import bv_compact, bv_from_numpy, bv_popcount
+
+    flush("compaction with tail bits, n=%d" % n)
+    R = datagen.random_mask_words(n, seed=n + 11, density=density)
+    want_ids = bv_row_ids(R, n)
+    dirty = R.copy()
+    if n % 64:
+        dirty[-1] |= np.uint64(~((1 << (n % 64)) - 1) & 0xFFFFFFFFFFFFFFFF)   # garbage past the last row
+    Rt = bv_from_numpy(dirty)
+    assert int(bv_popcount(Rt, n).item()) == want_ids.shape[0]
+    ids, count = bv_compact(Rt, n, max(1, want_ids.shape[0]))
+    torch.cuda.synchronize()
+    assert int(count.item()) == want_ids.shape[0]
+    assert np.array_equal(_np32(ids)[: want_ids.shape[0]], want_ids)
+
+
 def test_compact_overflow_flag():
     from paper_2209_00220_amd.column import bv_compact, bv_from_numpy
 
