@@ -350,6 +350,17 @@ __device__ __forceinline__ uint32_t lookup_row(const DevCol& c, uint64_t r) {
             len = j;
         }
         if (c.categorical) return c.dict[categorical_rank(code, len, c.K)];
+        if (guided) {
+            // the walk above already reached the code's last node: a leaf turns
+            // its slot digits into a dictionary rank, an internal node's slot
+            // entry holds the value
+            if (node & kLeafFlag) {
+                const uint32_t beta = (node >> kLeafDigitsShift) & 7u;
+                const uint64_t slot = code & ((1ull << (8 * beta)) - 1);
+                return c.dict[leaf_base(c, node) + (uint32_t)slot - 1u];
+            }
+            return c.trie[((uint64_t)node * 256 + (uint32_t)(code & 0xffu)) * 2];
+        }
         return trie_value(c, code, len);
     }
     if (c.layout == BST_BYTESLICE) {
