@@ -41,11 +41,13 @@ template <int MODE>
 int launch_slices_mode(const DevCol& c, const ScanLit& lit, const uint64_t* in, uint64_t* out,
                        unsigned long long* counters, hipStream_t st) {
     // Workgroups per CU: 3 where the literal is settled by byte 1 (fewer
-    // concurrent streams read faster) and for ByteSlice; 4 for PP-VBS literals
-    // of several bytes, whose gathers and compares need more waves to keep HBM
-    // busy (measured on the 500M-row benchmark column: 5 % less time for those).
+    // concurrent streams read faster) and for ByteSlice '<', '>' and '='; 4 for
+    // PP-VBS literals of several bytes and ByteSlice BETWEEN, whose gathers and
+    // compares need more waves to keep HBM busy (measured on the 500M-row
+    // benchmark column: 5 % less time for the PP-VBS scans concerned, 1 % for
+    // the ByteSlice step).
     const bool byte1 = lit.llo == 1 && (MODE != kModeBetween || lit.lhi == 1);
-    const uint32_t per_cu = (c.layout == BST_PPVBS && !byte1) ? 4u : 3u;
+    const uint32_t per_cu = (!byte1 && (c.layout == BST_PPVBS || MODE == kModeBetween)) ? 4u : 3u;
     const uint32_t grid = tile_grid(c.ntiles, g_tune[BST_TUNE_SCAN_GRID], per_cu);
     if (counters) {
         launch_slices_s<MODE, -1, true>(grid, st, c, lit, in, out, counters);
