@@ -141,6 +141,31 @@ def test_compact_and_popcount_ignore_tail_bits(n, density):
     assert np.array_equal(_np32(ids)[: want_ids.shape[0]], want_ids)
 
 
+def test_compact_and_popcount_random_sizes():
+    """Compaction and popcount over 30 seeded (rows, density) pairs, from one
+    row to several chunks, each bitvector with garbage past its last row."""
+    from paper_2209_00220_amd.column import bv_compact, bv_from_numpy, bv_popcount
+
+    rng = np.random.default_rng(2024)
+    for i in range(30):
+        n = int(rng.integers(1, 700_000)) if i % 3 else int(rng.integers(1, 5000))
+        density = float(rng.choice([0.0, 0.001, 0.05, 0.5, 0.99, 1.0]))
+        flush("random compaction %d: n=%d density=%g" % (i, n, density))
+        R = datagen.random_mask_words(n, seed=1000 + i, density=density)
+        want_ids = bv_row_ids(R, n)
+        dirty = R.copy()
+        if n % 64:
+            dirty[-1] |= np.uint64(~((1 << (n % 64)) - 1) & 0xFFFFFFFFFFFFFFFF)
+        Rt = bv_from_numpy(dirty)
+        assert int(bv_popcount(Rt, n).item()) == want_ids.shape[0], (n, density)
+        cap = int(want_ids.shape[0]) if i % 5 else max(0, int(want_ids.shape[0]) - 3)   # sometimes too small
+        ids, count = bv_compact(Rt, n, cap)
+        torch.cuda.synchronize()
+        assert int(count.item()) == want_ids.shape[0], (n, density)
+        k = min(cap, want_ids.shape[0])
+        assert np.array_equal(_np32(ids)[:k], want_ids[:k]), (n, density)
+
+
 def test_compact_overflow_flag():
     from paper_2209_00220_amd.column import bv_compact, bv_from_numpy
 
