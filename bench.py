@@ -41,8 +41,8 @@ LAYOUTS = ("ppvbs", "byteslice", "bitpacked")
 KERNEL_SOURCES = ("paper_2209_00220_amd/csrc/device_common.h", "paper_2209_00220_amd/csrc/slice_scan.h",
                   "paper_2209_00220_amd/csrc/scan_kernel.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "scan_lookup_500M_traffic.txt")
-TRACE_CMD = "rocprofv3 --kernel-trace --stats -d gpurun_out/trace -o run --output-format csv -- python3 bench.py"
-PMC_CMDS = ["rocprofv3 --pmc %s -d gpurun_out/%s -o run --output-format csv -- python3 bench.py --steps 1 "
+TRACE_CMD = "rocprofv3 --kernel-trace --stats -d rocprof_out/trace -o run --output-format csv -- python3 bench.py"
+PMC_CMDS = ["rocprofv3 --pmc %s -d rocprof_out/%s -o run --output-format csv -- python3 bench.py --steps 1 "
             "--warmup 0 --no-batch --serve-queries 0 --no-cpu-baseline --copy-calibration" % (c, d)
             for c, d in (("FETCH_SIZE", "pmc_fetch"), ("WRITE_SIZE", "pmc_write"))]
 
@@ -209,7 +209,7 @@ def summarize_trace(trace_dir: str, steps: int, warmup: int, cmd: str, out_path:
              "",
              "commands (repo root; TMPDIR=/tmp):",
              "  " + cmd,
-             "  python3 bench.py --summarize-trace gpurun_out/trace --out profiles/scan_lookup_500M_kernel_trace.txt",
+             "  python3 bench.py --summarize-trace rocprof_out/trace --out profiles/scan_lookup_500M_kernel_trace.txt",
              "",
              "timed steps only (per launch, from the trace's start/end stamps, microseconds):",
              "  %-12s %6s %10s %10s %10s" % ("group", "calls", "avg_us", "min_us", "max_us")]
@@ -234,7 +234,7 @@ def summarize_trace(trace_dir: str, steps: int, warmup: int, cmd: str, out_path:
         f.write("\n".join(lines) + "\n")
 
 
-BATCH_TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d gpurun_out/batchtrace -o run --output-format csv -- "
+BATCH_TRACE_CMD = ("rocprofv3 --kernel-trace --stats -d rocprof_out/batchtrace -o run --output-format csv -- "
                    "python3 bench.py --workload batch")
 
 
@@ -274,8 +274,8 @@ def summarize_batch_trace(trace_dir: str, bench_json: str, out_path: str, n_pred
              "[0, 1.5]), 4.66 G rows scanned per pass.",
              "",
              "commands (repo root; TMPDIR=/tmp):",
-             "  " + BATCH_TRACE_CMD + " > gpurun_out/batchtrace.out",
-             "  python3 bench.py --summarize-batch-trace gpurun_out/batchtrace gpurun_out/batchtrace.out "
+             "  " + BATCH_TRACE_CMD + " > rocprof_out/batchtrace.out",
+             "  python3 bench.py --summarize-batch-trace rocprof_out/batchtrace rocprof_out/batchtrace.out "
              "--out profiles/batch_256preds_64cols_kernel_trace.txt",
              "",
              "%d single launches per pass (the tuned single-column launch shape), last %d passes; span = first" % (
@@ -343,9 +343,9 @@ def summarize_counters(fetch_dir: str, write_dir: str, cmds, out_path: str, pred
              "sources these counters were taken on (bench.py reports roofline.traffic only when it",
              "matches the current sources).",
              "",
-             "commands (repo root; TMPDIR=/tmp; the first run's stdout goes to gpurun_out/pmc_fetch.out):"] +
+             "commands (repo root; TMPDIR=/tmp; the first run's stdout goes to rocprof_out/pmc_fetch.out):"] +
              ["  " + c for c in cmds] + [
-             "  python3 bench.py --summarize-pmc gpurun_out/pmc_fetch gpurun_out/pmc_write --out profiles/scan_lookup_500M_traffic.txt",
+             "  python3 bench.py --summarize-pmc rocprof_out/pmc_fetch rocprof_out/pmc_write --out profiles/scan_lookup_500M_traffic.txt",
              "",
              "Per scan, beside the measured traffic, the kernel's own byte counters (bst_scan_stats, MB):",
              "alg128 = algorithmic bytes at 128-byte granularity, exact = the same bytes exactly,",
@@ -393,7 +393,7 @@ def summarize_counters(fetch_dir: str, write_dir: str, cmds, out_path: str, pred
         f.write("\n".join(lines) + "\n")
 
 
-WAIT_CMD = ("rocprofv3 --pmc SQ_WAIT_ANY SQ_WAVE_CYCLES -d gpurun_out/pmc_wait -o run --output-format csv -- "
+WAIT_CMD = ("rocprofv3 --pmc SQ_WAIT_ANY SQ_WAVE_CYCLES -d rocprof_out/pmc_wait -o run --output-format csv -- "
             "python3 bench.py --steps 1 --warmup 0 --no-batch --serve-queries 0 --no-cpu-baseline")
 
 
@@ -416,7 +416,7 @@ def summarize_wait(wait_dir: str, out_path: str, preds, layouts=LAYOUTS):
              "",
              "commands (repo root; TMPDIR=/tmp):",
              "  " + WAIT_CMD,
-             "  python3 bench.py --summarize-wait gpurun_out/pmc_wait --out profiles/scan_lookup_500M_wait.txt",
+             "  python3 bench.py --summarize-wait rocprof_out/pmc_wait --out profiles/scan_lookup_500M_wait.txt",
              ""]
     cur = None
     for (lay, i), r in zip(order, steps):
